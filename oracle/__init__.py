@@ -1,0 +1,123 @@
+"""CPU FP64 oracle for the regularized Stokes single layer.
+
+TEST INFRASTRUCTURE ONLY.  Imported by the tests, by the smoke check and by the
+benchmark's CPU-baseline leg; the product library never imports or links it and
+shares no code with it.  The arithmetic lives in ``slref.c`` (plain C, glibc
+erf/exp, Neumaier sums, OpenMP over targets); this module only builds and loads
+it and marshals numpy arrays.
+
+Pinned by ``tests/test_oracle_pins.py`` against the r -> 0 limits stated in
+Sec. 3.4, vanishing moments of s - 1, the sphere's closed-form drag and
+rotation velocities, S[n] = 0 with the O(delta^5) order, the discrete
+reciprocity identity, translation/rotation invariance and a 40-digit brute
+force on tiny inputs.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "slref.c")
+LIB_PATH = os.path.join(_HERE, "libslref.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile slref.c into libslref.so next to it (gcc -O2 -fopenmp, no fast-math)."""
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + f".tmp{os.getpid()}"
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+               "-fno-fast-math", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build(force=False)
+        lib = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER(ctypes.c_double)
+        i64, d = ctypes.c_int64, ctypes.c_double
+        lib.slref_eval.argtypes = [i64, P, P, P, P, P, P, P, i64, P, P, P, d, P, d, P, P, P,
+                                   ctypes.c_int]
+        lib.slref_eval.restype = ctypes.c_int
+        lib.slref_smoothing.argtypes = [d, P, P]
+        lib.slref_smoothing.restype = None
+        lib.slref_kernel.argtypes = [d, d, P, P]
+        lib.slref_kernel.restype = None
+        lib.slref_max_threads.argtypes = []
+        lib.slref_max_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _col(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def single_layer(X, w, f, delta, mu=1.0, targets=None, delta_tgt=None, nthreads=0):
+    """u (n_tgt, 3) at `targets` (default: the source nodes X) from sources X (N, 3),
+    weights w (N,), density f (N, 3)."""
+    lib = _load()
+    X = np.asarray(X, dtype=np.float64)
+    f = np.asarray(f, dtype=np.float64)
+    sx, sy, sz = _col(X[:, 0]), _col(X[:, 1]), _col(X[:, 2])
+    fx, fy, fz = _col(f[:, 0]), _col(f[:, 1]), _col(f[:, 2])
+    w = _col(w)
+    if targets is None:
+        nt = X.shape[0]
+        tx = ty = tz = None
+    else:
+        T = np.asarray(targets, dtype=np.float64).reshape(-1, 3)
+        nt = T.shape[0]
+        tx, ty, tz = _col(T[:, 0]), _col(T[:, 1]), _col(T[:, 2])
+    dt = None if delta_tgt is None else _col(delta_tgt)
+    if dt is not None and dt.shape[0] != nt:
+        raise ValueError("delta_tgt must have one entry per target")
+    ux, uy, uz = (np.zeros(nt) for _ in range(3))
+    rc = lib.slref_eval(X.shape[0], _ptr(sx), _ptr(sy), _ptr(sz), _ptr(w), _ptr(fx), _ptr(fy),
+                        _ptr(fz), nt, _ptr(tx), _ptr(ty), _ptr(tz), float(delta), _ptr(dt),
+                        float(mu), _ptr(ux), _ptr(uy), _ptr(uz), int(nthreads))
+    if rc != 0:
+        raise ValueError("slref_eval rejected its arguments")
+    return np.stack([ux, uy, uz], axis=1)
+
+
+def smoothing(p: float):
+    """(s1(p), s2(p)) as printed in Sec. 3.4."""
+    lib = _load()
+    a, b = ctypes.c_double(), ctypes.c_double()
+    lib.slref_smoothing(float(p), ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+def kernel(r: float, delta: float):
+    """(s1(r/delta)/r, s2(r/delta)/r^3), with the r = 0 limits."""
+    lib = _load()
+    a, b = ctypes.c_double(), ctypes.c_double()
+    lib.slref_kernel(float(r), float(delta), ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+def max_threads() -> int:
+    return int(_load().slref_max_threads())
+
+
+def rel_inf_error(u, u_ref) -> float:
+    """eps = ||u - u_ref||_inf / ||u_ref||_inf over all targets and components (Sec. 4.1)."""
+    u, u_ref = np.asarray(u), np.asarray(u_ref)
+    return float(np.max(np.abs(u - u_ref)) / np.max(np.abs(u_ref)))

@@ -1,0 +1,149 @@
+/*
+ * stokeslet.h -- C ABI of the MI355X (gfx950) regularized Stokes single-layer library.
+ *
+ * The operation (Agarwal & Biros, Sec. 3.4, eq. (regstokes), discretized with the
+ * trapezoid-POU rule of Sec. 3.3, eq. (smoothint)):
+ *
+ *   u_i = 1/(8 pi mu) * sum_j w_j [ s1(r/d)/r f_j + s2(r/d)/r^3 (f_j . x_ij) x_ij ],
+ *   x_ij = t_i - x_j,  r = |x_ij|,  d = delta (or delta_tgt[i]),
+ *   s1(p) = erf p - (2/3) p (2p^2 - 5) e^{-p^2}/sqrt(pi),
+ *   s2(p) = erf p - (2/3) p (4p^4 - 14p^2 + 3) e^{-p^2}/sqrt(pi),
+ *
+ * with the r = 0 limit s1(r/d)/r -> 16/(3 d sqrt(pi)) (Sec. 3.4); the pair with r = 0
+ * contributes only that term.  Every source is summed for every target, including a
+ * target that coincides with a source.
+ *
+ * Conventions shared by every entry point:
+ *  - Arrays are structure-of-arrays, IEEE double, in DEVICE memory of the context's GPU
+ *    (e.g. torch tensors' data_ptr()).  Positions and densities are not scanned: NaN/Inf
+ *    propagate into the affected outputs.
+ *  - The caller owns every array it passes; the library never frees caller memory.
+ *    Arrays passed to an asynchronous call must stay valid until that work completes.
+ *  - Outputs must not alias inputs.
+ *  - A status code is returned; on failure sl_last_error() gives a message (per thread).
+ *    Invalid arguments are rejected before any GPU work is enqueued.
+ */
+#ifndef STOKESLET_H
+#define STOKESLET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SL_OK = 0,
+    SL_EINVAL = -1,     /* bad argument: NULL pointer, n < 0, delta/mu not finite and > 0, aliasing */
+    SL_ENOMEM = -2,     /* device allocation failed */
+    SL_EBUSY = -3,      /* admission refused: the HBM budget is exhausted */
+    SL_EHIP = -4,       /* a HIP runtime call or a kernel launch failed */
+    SL_ENOTFOUND = -5,  /* unknown surface handle or request id */
+    SL_ETIMEDOUT = -6   /* sl_wait gave up before the request completed */
+} sl_status;
+
+typedef enum {
+    SL_FP64 = 0,        /* every pair in double precision; ~1e-15 relative to the exact sum */
+    SL_MIXED = 1        /* far pairs in single precision with two-sum compensated per-target
+                           accumulation; pairs near the target (rho = r/delta below the FP64
+                           cut, default 5), the self term and the final per-target sum in
+                           double precision; ~1e-7 relative */
+} sl_precision;
+
+typedef struct sl_ctx sl_ctx;   /* opaque; one per device */
+
+/* Create a context on HIP device `device`.  `hbm_budget_bytes` bounds the device memory
+ * held by resident surfaces and in-flight serving requests (0 = 90% of the free memory at
+ * creation).  One-shot sl_eval calls allocate their workspace stream-ordered and are not
+ * counted against the budget.  Returns SL_EINVAL for a bad device or NULL `out`. */
+sl_status sl_create(int device, size_t hbm_budget_bytes, sl_ctx **out);
+
+/* Drain the serving queue, stop its persistent kernel and free everything the context owns.
+ * NULL is a no-op. */
+void sl_destroy(sl_ctx *ctx);
+
+/* Message describing the last failure on the calling thread ("" if none).  The pointer is
+ * valid until the next library call on that thread. */
+const char *sl_last_error(void);
+
+/* Tunables.  SL_PARAM_RHO64: in SL_MIXED, pairs with r/delta below this value are summed in
+ * double precision (the single-precision zone needs r/delta >= 5, where s1 = s2 = 1 to single
+ * precision; values below 5 are rejected).  Default 5. */
+typedef enum { SL_PARAM_RHO64 = 0 } sl_param;
+sl_status sl_set_param(sl_ctx *ctx, sl_param key, double value);
+sl_status sl_get_param(const sl_ctx *ctx, sl_param key, double *value);
+
+/*
+ * One-shot evaluation, asynchronous on `stream` (a hipStream_t; NULL = the null stream).
+ *
+ *  sources:  n_src >= 0 nodes sx, sy, sz; quadrature weights w (Sec. 3.3: psi W h^2);
+ *            density fx, fy, fz.
+ *  targets:  n_tgt >= 0 points tx, ty, tz.  tx == ty == tz == NULL means targets = sources
+ *            (then n_tgt must equal n_src).
+ *  delta:    regularization length (> 0, finite) used for every target when delta_tgt is NULL;
+ *            otherwise delta_tgt[n_tgt] gives one value per target (each > 0 and finite; not
+ *            checked on the device -- a non-positive entry yields NaN for that target) and
+ *            `delta` is ignored.
+ *  mu:       viscosity (> 0, finite).
+ *  output:   ux, uy, uz[n_tgt] (overwritten).
+ *
+ * n_src == 0 writes zeros; n_tgt == 0 enqueues nothing.  The call enqueues a spatial sort of
+ * the points, the packing of w*f, the pair kernels and the final per-target reduction; the
+ * workspace is allocated and freed stream-ordered on `stream`.  Results are deterministic:
+ * identical inputs give bit-identical outputs.
+ */
+sl_status sl_eval(sl_ctx *ctx, sl_precision prec,
+                  int64_t n_src, const double *sx, const double *sy, const double *sz,
+                  const double *w, const double *fx, const double *fy, const double *fz,
+                  int64_t n_tgt, const double *tx, const double *ty, const double *tz,
+                  double delta, const double *delta_tgt, double mu,
+                  double *ux, double *uy, double *uz, void *stream);
+
+/*
+ * Serving: device-resident surfaces and continuous batching.
+ *
+ * sl_surface_register copies n nodes (x, y, z, w: device arrays) into library-owned HBM,
+ * sorts them spatially once and keeps them resident; targets are the nodes themselves and
+ * delta is fixed per surface.  It is synchronous.  Admission: SL_EBUSY if the surface's
+ * footprint does not fit the remaining budget.
+ *
+ * sl_surface_release drops the handle; its memory is returned once no submitted request on
+ * it is still in flight.
+ *
+ * sl_submit enqueues u = S[f] on a resident surface: fx, fy, fz (density) and ux, uy, uz
+ * (output) are caller device arrays of the surface's n, valid until the request completes.
+ * The request's work (one item per block of targets) joins the queue of a single persistent
+ * kernel that serves every in-flight request; requests submitted while others run are
+ * interleaved with them on the device.  Each request's result is bit-identical to the same
+ * request served alone.  Admission: SL_EBUSY if the request's staging memory does not fit.
+ * Thread-safe.
+ *
+ * sl_poll sets *done to 1 when the request's output is complete and visible to later stream
+ * work and host copies, else 0.  sl_wait blocks until then or `timeout_s` seconds
+ * (SL_ETIMEDOUT).  A request id is retired by the first sl_poll/sl_wait that reports it done;
+ * later queries return SL_ENOTFOUND.
+ */
+sl_status sl_surface_register(sl_ctx *ctx, int64_t n, const double *x, const double *y,
+                              const double *z, const double *w, double delta, uint64_t *handle);
+sl_status sl_surface_release(sl_ctx *ctx, uint64_t handle);
+sl_status sl_submit(sl_ctx *ctx, uint64_t handle, sl_precision prec,
+                    const double *fx, const double *fy, const double *fz, double mu,
+                    double *ux, double *uy, double *uz, uint64_t *request);
+sl_status sl_poll(sl_ctx *ctx, uint64_t request, int *done);
+sl_status sl_wait(sl_ctx *ctx, uint64_t request, double timeout_s);
+
+/* Serving statistics since sl_create (for reporting): requests completed, work items
+ * executed, persistent-kernel launches, bytes currently admitted. */
+typedef struct {
+    uint64_t requests_done;
+    uint64_t items_done;
+    uint64_t kernel_launches;
+    uint64_t bytes_admitted;
+} sl_stats;
+sl_status sl_get_stats(const sl_ctx *ctx, sl_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STOKESLET_H */

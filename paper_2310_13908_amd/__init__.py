@@ -1,0 +1,83 @@
+"""MI355X (gfx950) regularized Stokes single layer (Agarwal & Biros, Sec. 3.4).
+
+The computation lives in ``libstokeslet.so`` (hand-written HIP, C ABI in
+``include/stokeslet.h``).  This package is its binding: ``_binding`` mirrors the C entry points
+under the same names; the helpers below only marshal torch tensors (device memory and the
+current stream) into those calls.
+"""
+from __future__ import annotations
+
+from . import _binding
+from ._binding import (EXPORTED, SL_EBUSY, SL_EHIP, SL_EINVAL, SL_ENOMEM, SL_ENOTFOUND, SL_ETIMEDOUT,
+                       SL_FP64, SL_MIXED, SL_OK, SL_PARAM_RHO64, SlError, check, load, sl_create,
+                       sl_destroy, sl_eval, sl_get_param, sl_get_stats, sl_last_error, sl_poll,
+                       sl_set_param, sl_submit, sl_surface_register, sl_surface_release, sl_wait)
+
+PRECISIONS = {"fp64": SL_FP64, "mixed": SL_MIXED}
+
+
+def _soa(t, n_cols=3):
+    """(n, 3) tensor -> contiguous (3, n) float64 tensor on the same device."""
+    import torch
+    t = t.to(torch.float64)
+    return t.reshape(-1, n_cols).t().contiguous()
+
+
+def _stream_handle(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class Context:
+    """Owns an ``sl_ctx`` on one device."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.device = device
+        self.ptr = sl_create(device, hbm_budget_bytes)
+
+    def close(self):
+        if self.ptr is not None and self.ptr.value:
+            sl_destroy(self.ptr)
+        self.ptr = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_rho64(self, value: float):
+        check(sl_set_param(self.ptr, SL_PARAM_RHO64, value), "sl_set_param")
+
+    def single_layer(self, X, w, f, delta, mu=1.0, targets=None, delta_tgt=None,
+                     precision="fp64", stream=None, out=None):
+        """u (n_tgt, 3) float64 on the device from torch device tensors X (N, 3), w (N,), f (N, 3).
+
+        Enqueued on the current torch stream (or `stream`); returns without synchronizing.
+        """
+        import torch
+        prec = PRECISIONS[precision]
+        Xs, fs = _soa(X), _soa(f)
+        ws = w.to(torch.float64).contiguous()
+        n_src = Xs.shape[1]
+        if targets is None:
+            Ts, n_tgt, tp = None, n_src, (None, None, None)
+        else:
+            Ts = _soa(targets)
+            n_tgt = Ts.shape[1]
+            tp = (Ts[0].data_ptr(), Ts[1].data_ptr(), Ts[2].data_ptr())
+        dts = None if delta_tgt is None else delta_tgt.to(torch.float64).contiguous()
+        U = out if out is not None else torch.empty((3, n_tgt), dtype=torch.float64, device=Xs.device)
+        st = sl_eval(self.ptr, prec, n_src, Xs[0].data_ptr(), Xs[1].data_ptr(), Xs[2].data_ptr(),
+                     ws.data_ptr(), fs[0].data_ptr(), fs[1].data_ptr(), fs[2].data_ptr(), n_tgt,
+                     *tp, float(delta), None if dts is None else dts.data_ptr(), float(mu),
+                     U[0].data_ptr(), U[1].data_ptr(), U[2].data_ptr(), _stream_handle(stream))
+        check(st, "sl_eval")
+        return U.t()

@@ -1,0 +1,260 @@
+// sl_api.hip -- C ABI entry points: context, parameters, one-shot evaluation.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "sl_internal.h"
+
+namespace sl {
+
+namespace {
+thread_local std::string g_last_error;
+
+// Makes the context's device current for the duration of a call and restores the caller's.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+struct Range {
+    const void *p;
+    int64_t bytes;
+};
+
+bool overlaps(const Range &a, const Range &b)
+{
+    if (!a.p || !b.p || a.bytes <= 0 || b.bytes <= 0) return false;
+    const char *a0 = (const char *)a.p, *b0 = (const char *)b.p;
+    return a0 < b0 + b.bytes && b0 < a0 + a.bytes;
+}
+
+bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+constexpr int64_t kMaxPoints = (int64_t)1 << 30;
+constexpr int kTargetsPerLane = 2;
+constexpr int kWavesPerSimd = 4;
+
+}  // namespace
+
+sl_status fail(sl_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+sl_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(e == hipErrorOutOfMemory ? SL_ENOMEM : SL_EHIP,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Workspace of one sl_eval call, carved from a single stream-ordered allocation.
+struct EvalWorkspace {
+    PackScratch ps;
+    SrcOut so;
+    TgtOut to;
+    double *part;
+};
+
+static size_t carve(char *base, EvalWorkspace &w, int64_t n_sort, int64_t np_s, int64_t np_t,
+                    bool distinct, bool mixed, bool vard, int n_splits)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += (size_t)round_up((int64_t)bytes, 256);
+        return p;
+    };
+    char *sort_base = take(sort_scratch_bytes(n_sort));
+    if (base) carve_sort_scratch(sort_base, n_sort, w.ps);
+    memset(&w.so, 0, sizeof(w.so));
+    memset(&w.to, 0, sizeof(w.to));
+    w.so.x = (double *)take(np_s * 8); w.so.y = (double *)take(np_s * 8); w.so.z = (double *)take(np_s * 8);
+    w.so.gx = (double *)take(np_s * 8); w.so.gy = (double *)take(np_s * 8); w.so.gz = (double *)take(np_s * 8);
+    if (mixed) {
+        w.so.x32 = (float *)take(np_s * 4); w.so.y32 = (float *)take(np_s * 4); w.so.z32 = (float *)take(np_s * 4);
+        w.so.gx32 = (float *)take(np_s * 4); w.so.gy32 = (float *)take(np_s * 4); w.so.gz32 = (float *)take(np_s * 4);
+    }
+    w.so.sphere = (double4 *)take(np_s / kCluster * sizeof(double4));
+    if (!distinct) w.so.perm = (int32_t *)take(np_s * 4);
+    if (distinct) {
+        w.to.x = (double *)take(np_t * 8); w.to.y = (double *)take(np_t * 8); w.to.z = (double *)take(np_t * 8);
+        if (mixed) {
+            w.to.x32 = (float *)take(np_t * 4); w.to.y32 = (float *)take(np_t * 4); w.to.z32 = (float *)take(np_t * 4);
+        }
+        w.to.perm = (int32_t *)take(np_t * 4);
+    }
+    if (vard) w.to.delta = (double *)take(np_t * 8);
+    w.part = (double *)take((size_t)n_splits * 3 * np_t * 8);
+    return off;
+}
+
+}  // namespace sl
+
+using namespace sl;
+
+extern "C" {
+
+const char *sl_last_error(void) { return g_last_error.c_str(); }
+
+sl_status sl_create(int device, size_t hbm_budget_bytes, sl_ctx **out)
+{
+    g_last_error.clear();
+    if (!out) return fail(SL_EINVAL, "sl_create: out is NULL");
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
+        return fail(SL_EINVAL, "sl_create: no such HIP device");
+    DeviceGuard g(device);
+    if (!g.ok) return fail(SL_EHIP, "sl_create: hipSetDevice failed");
+    hipDeviceProp_t prop;
+    SL_HIP(hipGetDeviceProperties(&prop, device));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(SL_EINVAL, std::string("sl_create: built for gfx950, device is ") + prop.gcnArchName);
+    size_t free_b = 0, total_b = 0;
+    SL_HIP(hipMemGetInfo(&free_b, &total_b));
+    sl_ctx *c = new sl_ctx();
+    c->device = device;
+    c->n_cu = prop.multiProcessorCount;
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
+    *out = c;
+    return SL_OK;
+}
+
+sl_status sl_set_param(sl_ctx *ctx, sl_param key, double value)
+{
+    if (!ctx) return fail(SL_EINVAL, "sl_set_param: ctx is NULL");
+    if (key == SL_PARAM_RHO64) {
+        if (!isfinite(value) || value < kRhoExact32)
+            return fail(SL_EINVAL, "sl_set_param: rho64 must be finite and >= 5");
+        std::lock_guard<std::mutex> l(ctx->mu);
+        ctx->rho64 = value;
+        return SL_OK;
+    }
+    return fail(SL_EINVAL, "sl_set_param: unknown key");
+}
+
+sl_status sl_get_param(const sl_ctx *ctx, sl_param key, double *value)
+{
+    if (!ctx || !value) return fail(SL_EINVAL, "sl_get_param: NULL argument");
+    if (key == SL_PARAM_RHO64) {
+        *value = ctx->rho64;
+        return SL_OK;
+    }
+    return fail(SL_EINVAL, "sl_get_param: unknown key");
+}
+
+sl_status sl_eval(sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *sx,
+                  const double *sy, const double *sz, const double *w, const double *fx,
+                  const double *fy, const double *fz, int64_t n_tgt, const double *tx,
+                  const double *ty, const double *tz, double delta, const double *delta_tgt,
+                  double mu, double *ux, double *uy, double *uz, void *stream)
+{
+    g_last_error.clear();
+    if (!ctx) return fail(SL_EINVAL, "sl_eval: ctx is NULL");
+    if (prec != SL_FP64 && prec != SL_MIXED) return fail(SL_EINVAL, "sl_eval: unknown precision");
+    if (n_src < 0 || n_tgt < 0) return fail(SL_EINVAL, "sl_eval: negative size");
+    if (n_src > kMaxPoints || n_tgt > kMaxPoints) return fail(SL_EINVAL, "sl_eval: more than 2^30 points");
+    if (!finite_pos(mu)) return fail(SL_EINVAL, "sl_eval: mu must be finite and > 0");
+    if (!delta_tgt && !finite_pos(delta)) return fail(SL_EINVAL, "sl_eval: delta must be finite and > 0");
+    const bool same = !tx && !ty && !tz;
+    if (!same && (!tx || !ty || !tz)) return fail(SL_EINVAL, "sl_eval: tx, ty, tz must be all NULL or all set");
+    if (same && n_tgt != n_src) return fail(SL_EINVAL, "sl_eval: targets = sources needs n_tgt == n_src");
+    if (n_tgt > 0 && (!ux || !uy || !uz)) return fail(SL_EINVAL, "sl_eval: output pointer is NULL");
+    if (n_src > 0 && (!sx || !sy || !sz || !w || !fx || !fy || !fz))
+        return fail(SL_EINVAL, "sl_eval: source pointer is NULL");
+    {
+        const Range outs[3] = {{ux, n_tgt * 8}, {uy, n_tgt * 8}, {uz, n_tgt * 8}};
+        const Range ins[11] = {{sx, n_src * 8}, {sy, n_src * 8}, {sz, n_src * 8}, {w, n_src * 8},
+                               {fx, n_src * 8}, {fy, n_src * 8}, {fz, n_src * 8}, {tx, n_tgt * 8},
+                               {ty, n_tgt * 8}, {tz, n_tgt * 8}, {delta_tgt, n_tgt * 8}};
+        for (int a = 0; a < 3; ++a) {
+            for (int b = a + 1; b < 3; ++b)
+                if (overlaps(outs[a], outs[b])) return fail(SL_EINVAL, "sl_eval: outputs overlap");
+            for (const Range &r : ins)
+                if (overlaps(outs[a], r)) return fail(SL_EINVAL, "sl_eval: output aliases an input");
+        }
+    }
+    if (n_tgt == 0) return SL_OK;
+
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(SL_EHIP, "sl_eval: hipSetDevice failed");
+    hipStream_t st = (hipStream_t)stream;
+    if (n_src == 0) {
+        SL_HIP(launch_fill_zero(ux, uy, uz, n_tgt, st));
+        return SL_OK;
+    }
+
+    const bool mixed = prec == SL_MIXED;
+    const bool vard = delta_tgt != nullptr;
+    const int64_t np_s = round_up(n_src, kPad);
+    const int64_t np_t = same ? np_s : round_up(n_tgt, kPad);
+    const int64_t n_sort = std::max(n_src, same ? (int64_t)0 : n_tgt);
+    const PairPlan plan = plan_pairs(np_s, np_t, kTargetsPerLane, ctx->n_cu * 4 * kWavesPerSimd);
+
+    EvalWorkspace ws;
+    const size_t bytes = carve(nullptr, ws, n_sort, np_s, np_t, !same, mixed, vard, plan.n_splits);
+    char *base = nullptr;
+    SL_HIP(hipMallocAsync((void **)&base, bytes, st));
+    carve(base, ws, n_sort, np_s, np_t, !same, mixed, vard, plan.n_splits);
+
+    hipError_t e = launch_bbox(sx, sy, sz, n_src, tx, ty, tz, same ? 0 : n_tgt, ws.ps, st);
+    const uint32_t *order = nullptr;
+    if (e == hipSuccess) e = launch_sort_points(sx, sy, sz, n_src, ws.ps, &order, st);
+    if (e == hipSuccess)
+        e = launch_gather_src(order, n_src, np_s, sx, sy, sz, w, fx, fy, fz, ws.ps.centre, ws.so, st);
+    TgtView tv;
+    if (same) {
+        tv.x = ws.so.x; tv.y = ws.so.y; tv.z = ws.so.z;
+        tv.x32 = ws.so.x32; tv.y32 = ws.so.y32; tv.z32 = ws.so.z32;
+        tv.perm = ws.so.perm;
+        if (vard && e == hipSuccess) {
+            TgtOut d = {};
+            d.delta = ws.to.delta;
+            e = launch_gather_tgt(order, n_tgt, np_t, nullptr, nullptr, nullptr, delta_tgt,
+                                  ws.ps.centre, d, st);
+        }
+    } else {
+        if (e == hipSuccess) e = launch_sort_points(tx, ty, tz, n_tgt, ws.ps, &order, st);
+        if (e == hipSuccess)
+            e = launch_gather_tgt(order, n_tgt, np_t, tx, ty, tz, delta_tgt, ws.ps.centre, ws.to, st);
+        tv.x = ws.to.x; tv.y = ws.to.y; tv.z = ws.to.z;
+        tv.x32 = ws.to.x32; tv.y32 = ws.to.y32; tv.z32 = ws.to.z32;
+        tv.perm = ws.to.perm;
+    }
+    tv.delta = vard ? ws.to.delta : nullptr;
+    tv.np = np_t;
+    tv.n = n_tgt;
+
+    PairArgs pa;
+    pa.s = SrcView{ws.so.x, ws.so.y, ws.so.z, ws.so.gx, ws.so.gy, ws.so.gz,
+                   ws.so.x32, ws.so.y32, ws.so.z32, ws.so.gx32, ws.so.gy32, ws.so.gz32,
+                   ws.so.sphere, np_s};
+    pa.t = tv;
+    pa.delta = vard ? 1.0 : delta;
+    pa.far_cut = mixed ? ctx->rho64 : kRhoExact64;
+    pa.clusters_per_split = plan.clusters_per_split;
+    pa.n_splits = plan.n_splits;
+    pa.n_tblocks = plan.n_tblocks;
+    pa.part = ws.part;
+    pa.bbox = ws.ps.bbox;
+    if (e == hipSuccess) e = launch_pair(pa, plan, mixed, vard, st);
+    if (e == hipSuccess)
+        e = launch_reduce(ws.part, plan.n_splits, np_t, tv.perm, 1.0 / (8.0 * M_PI * mu), ux, uy, uz, st);
+    const hipError_t ef = hipFreeAsync(base, st);
+    if (e != hipSuccess) return hip_fail(e, "sl_eval: kernel launch");
+    if (ef != hipSuccess) return hip_fail(ef, "sl_eval: hipFreeAsync");
+    return SL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+// sl_internal.h -- host-side declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "stokeslet.h"
+#include "sl_device.h"
+
+namespace sl {
+
+// ---------------------------------------------------------------------------------------
+// Error reporting
+// ---------------------------------------------------------------------------------------
+sl_status fail(sl_status s, const std::string &msg);
+sl_status hip_fail(hipError_t e, const char *what);
+#define SL_HIP(call)                                              \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return ::sl::hip_fail(e_, #call);   \
+    } while (0)
+
+inline int64_t round_up(int64_t n, int64_t m) { return (n + m - 1) / m * m; }
+
+// ---------------------------------------------------------------------------------------
+// Sorted, padded point sets ("packed" layout in HBM)
+// ---------------------------------------------------------------------------------------
+// Sources after the spatial sort: np = round_up(n, kPad) entries; entries n..np-1 repeat the
+// last real node with zero density.  Clusters of 64 consecutive sources carry a bounding
+// sphere (centre x, y, z, radius).
+struct SrcView {
+    const double *x, *y, *z;       // sorted positions
+    const double *gx, *gy, *gz;    // sorted w * f
+    const float *x32, *y32, *z32;  // positions minus `centre`, single precision (mixed only)
+    const float *gx32, *gy32, *gz32;
+    const double4 *sphere;         // [np / 64]
+    int64_t np;
+};
+
+// Targets after the spatial sort, padded the same way.  perm[p] is the caller's index of
+// sorted target p, or -1 for padding.
+struct TgtView {
+    const double *x, *y, *z;
+    const float *x32, *y32, *z32;
+    const double *delta;           // per-target delta (nullptr: scalar delta)
+    const int32_t *perm;
+    int64_t np;
+    int64_t n;
+};
+
+struct PairArgs {
+    SrcView s;
+    TgtView t;
+    double delta;            // scalar delta when t.delta == nullptr
+    double far_cut;          // cluster far test: gap >= far_cut * delta_max
+    int64_t clusters_per_split;
+    int n_splits;
+    int n_tblocks;
+    double *part;            // [n_splits][3][t.np] partial sums (unscaled)
+    const double *bbox;      // [6] box of all points (min xyz, max xyz): bounds the rounding
+                             // of the single-precision positions in the mixed path
+};
+
+// Launch configuration chosen by the host for a given problem.
+struct PairPlan {
+    int R;                   // targets per lane
+    int n_tblocks;
+    int n_splits;
+    int64_t clusters_per_split;
+};
+
+PairPlan plan_pairs(int64_t np_src, int64_t np_tgt, int R, int waves_wanted);
+
+hipError_t launch_pair(const PairArgs &a, const PairPlan &p, bool mixed, bool var_delta,
+                       hipStream_t st);
+hipError_t launch_reduce(const double *part, int n_splits, int64_t np, const int32_t *perm,
+                         double scale, double *ux, double *uy, double *uz, hipStream_t st);
+hipError_t launch_fill_zero(double *ux, double *uy, double *uz, int64_t n, hipStream_t st);
+
+// ---------------------------------------------------------------------------------------
+// Packing: bounding box, Morton keys, stable radix sort, gather (sl_pack.hip)
+// ---------------------------------------------------------------------------------------
+struct PackScratch {
+    uint32_t *keys[2];
+    uint32_t *vals[2];
+    uint32_t *counts;        // [256 * n_chunks]
+    double *bbox_part;       // [kBboxBlocks * 6]
+    double *bbox;            // [6]: min x, y, z, max x, y, z
+    double *centre;          // [3]: bounding-box centre (origin of the single-precision copies)
+};
+
+size_t sort_scratch_bytes(int64_t n);
+void carve_sort_scratch(void *base, int64_t n, PackScratch &ps);
+
+// Bounding box of up to two point sets (b may be empty), written to ps.bbox / ps.centre.
+hipError_t launch_bbox(const double *ax, const double *ay, const double *az, int64_t na,
+                       const double *bx, const double *by, const double *bz, int64_t nb,
+                       const PackScratch &ps, hipStream_t st);
+// Morton order of n points: on return *order points to n indices (sorted by key, stable).
+hipError_t launch_sort_points(const double *x, const double *y, const double *z, int64_t n,
+                              const PackScratch &ps, const uint32_t **order, hipStream_t st);
+
+struct SrcOut {
+    double *x, *y, *z, *gx, *gy, *gz;
+    float *x32, *y32, *z32, *gx32, *gy32, *gz32;   // nullptr unless mixed
+    double4 *sphere;
+    int32_t *perm;                                  // optional: sorted -> caller index (-1 pad)
+};
+// g = w * f gathered in `order`; w may be nullptr when `wf_premul` (f already holds w*f).
+hipError_t launch_gather_src(const uint32_t *order, int64_t n, int64_t np, const double *x,
+                             const double *y, const double *z, const double *w, const double *fx,
+                             const double *fy, const double *fz, const double *centre,
+                             const SrcOut &o, hipStream_t st);
+
+struct TgtOut {
+    double *x, *y, *z;
+    float *x32, *y32, *z32;
+    double *delta;
+    int32_t *perm;
+};
+hipError_t launch_gather_tgt(const uint32_t *order, int64_t n, int64_t np, const double *x,
+                             const double *y, const double *z, const double *delta_in,
+                             const double *centre, const TgtOut &o, hipStream_t st);
+
+// Gather only the density of a resident surface in its stored order (serving path).
+hipError_t launch_gather_density(const int32_t *perm, int64_t n, int64_t np, const double *w,
+                                 const double *fx, const double *fy, const double *fz,
+                                 double *gx, double *gy, double *gz, float *gx32, float *gy32,
+                                 float *gz32, hipStream_t st);
+
+}  // namespace sl
+
+// ---------------------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------------------
+namespace sl {
+struct Server;   // serving runtime (sl_serve.hip)
+}
+
+struct sl_ctx {
+    int device = 0;
+    int n_cu = 0;
+    size_t budget = 0;
+    double rho64 = sl::kRhoExact32;
+    std::mutex mu;
+    sl::Server *server = nullptr;
+};

@@ -1,0 +1,383 @@
+// sl_pack.hip -- staging of the inputs of the single-layer sum on gfx950.
+//
+// The pair kernels classify whole blocks of targets against clusters of 64 sources as
+// "far" (plain Stokeslet, no erf/exp) or "near" (regularized), which only pays off when
+// consecutive points are close in space.  Packing therefore:
+//   1. takes the bounding box of all points (two-pass, deterministic),
+//   2. orders the points along a 30-bit Morton curve (stable LSD radix sort, 8-bit digits),
+//   3. gathers positions and the packed density g = w f (the trapezoid-POU weight of
+//      Sec. 3.3 folded into the force) into padded structure-of-arrays buffers, plus the
+//      single-precision copies used by the mixed path (positions relative to the box centre),
+//   4. computes one bounding sphere per cluster of 64 sources.
+// Everything is O(N) and runs on the caller's stream.
+#include "sl_internal.h"
+
+namespace sl {
+
+namespace {
+
+constexpr int kBboxBlocks = 256;
+constexpr int kBboxThreads = 256;
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortChunk = kSortThreads * kSortItems;   // elements per block and pass
+constexpr int kMortonBits = 10;                         // per axis
+
+// ----------------------------------------------------------------------------------------
+// Bounding box
+// ----------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBboxThreads) void k_bbox_partial(
+    const double *__restrict__ ax, const double *__restrict__ ay, const double *__restrict__ az,
+    int64_t na, const double *__restrict__ bx, const double *__restrict__ by,
+    const double *__restrict__ bz, int64_t nb, double *__restrict__ part)
+{
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < na + nb; i += stride) {
+        double p[3];
+        if (i < na) { p[0] = ax[i]; p[1] = ay[i]; p[2] = az[i]; }
+        else { p[0] = bx[i - na]; p[1] = by[i - na]; p[2] = bz[i - na]; }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { lo[k] = fmin(lo[k], p[k]); hi[k] = fmax(hi[k], p[k]); }
+    }
+    __shared__ double red[6][kBboxThreads / kWave];
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double l = wave_min(lo[k]), h = wave_max(hi[k]);
+        if (lane == 0) { red[k][w] = l; red[3 + k][w] = h; }
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        double v = red[k][0];
+        for (int j = 1; j < kBboxThreads / kWave; ++j) v = k < 3 ? fmin(v, red[k][j]) : fmax(v, red[k][j]);
+        part[blockIdx.x * 6 + k] = v;
+    }
+}
+
+__global__ __launch_bounds__(kWave) void k_bbox_final(const double *__restrict__ part, int nparts,
+                                                      double *__restrict__ bbox,
+                                                      double *__restrict__ centre)
+{
+    const int lane = threadIdx.x;
+    double v[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = k < 3 ? INFINITY : -INFINITY;
+    for (int j = lane; j < nparts; j += kWave)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v[k] = k < 3 ? fmin(v[k], part[j * 6 + k]) : fmax(v[k], part[j * 6 + k]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = k < 3 ? wave_min(v[k]) : wave_max(v[k]);
+    if (lane == 0) {
+        for (int k = 0; k < 6; ++k) bbox[k] = v[k];
+        for (int k = 0; k < 3; ++k) centre[k] = 0.5 * (v[k] + v[k + 3]);
+    }
+}
+
+// ----------------------------------------------------------------------------------------
+// Morton keys
+// ----------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t quantize(double v, double lo, double hi)
+{
+    const double span = hi - lo;
+    double t = span > 0.0 ? (v - lo) / span : 0.0;
+    t = t * (double)(1 << kMortonBits);
+    int q = (int)t;
+    q = q < 0 ? 0 : (q > (1 << kMortonBits) - 1 ? (1 << kMortonBits) - 1 : q);
+    return (uint32_t)q;
+}
+
+// Interleave: bit b of axis a goes to key bit 3 b + (2 - a)  (x is the most significant).
+__device__ __forceinline__ uint32_t morton3(uint32_t qx, uint32_t qy, uint32_t qz)
+{
+    uint32_t k = 0;
+#pragma unroll
+    for (int b = 0; b < kMortonBits; ++b) {
+        k |= ((qx >> b) & 1u) << (3 * b + 2);
+        k |= ((qy >> b) & 1u) << (3 * b + 1);
+        k |= ((qz >> b) & 1u) << (3 * b + 0);
+    }
+    return k;
+}
+
+__global__ __launch_bounds__(256) void k_morton(const double *__restrict__ x,
+                                                const double *__restrict__ y,
+                                                const double *__restrict__ z, int64_t n,
+                                                const double *__restrict__ bbox,
+                                                uint32_t *__restrict__ keys,
+                                                uint32_t *__restrict__ vals)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t qx = quantize(x[i], bbox[0], bbox[3]);
+    const uint32_t qy = quantize(y[i], bbox[1], bbox[4]);
+    const uint32_t qz = quantize(z[i], bbox[2], bbox[5]);
+    keys[i] = morton3(qx, qy, qz);
+    vals[i] = (uint32_t)i;
+}
+
+// ----------------------------------------------------------------------------------------
+// Stable LSD radix sort of (key, value) pairs, 8-bit digits.
+// Block b owns elements [b * kSortChunk, (b + 1) * kSortChunk) in every pass.
+// ----------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *__restrict__ keys,
+                                                          int64_t n, int shift,
+                                                          uint32_t *__restrict__ counts,
+                                                          int nblocks)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortChunk;
+    for (int k = 0; k < kSortItems; ++k) {
+        const int64_t i = base + k * kSortThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan, in place, of `total` counters laid out digit-major (one block).
+__global__ __launch_bounds__(1024) void k_rs_scan(uint32_t *__restrict__ counts, int64_t total)
+{
+    __shared__ uint32_t buf[2][1024];
+    const int t = threadIdx.x;
+    const int64_t per = (total + 1023) / 1024;
+    const int64_t b = t * per, e = b + per < total ? b + per : total;
+    uint32_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += counts[i];
+    buf[0][t] = s;
+    __syncthreads();
+    int src = 0;
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t v = buf[src][t] + (t >= off ? buf[src][t - off] : 0u);
+        buf[src ^ 1][t] = v;
+        src ^= 1;
+        __syncthreads();
+    }
+    uint32_t run = buf[src][t] - s;   // exclusive prefix of this thread's segment
+    for (int64_t i = b; i < e; ++i) {
+        const uint32_t c = counts[i];
+        counts[i] = run;
+        run += c;
+    }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_rs_scatter(
+    const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+    uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n, int shift,
+    const uint32_t *__restrict__ offs, int nblocks)
+{
+    constexpr int kWaves = kSortThreads / kWave;
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t cnt[kWaves][256];
+    const int t = threadIdx.x, w = t / kWave, lane = t % kWave;
+    base[t] = offs[(int64_t)t * nblocks + blockIdx.x];
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const int64_t start = (int64_t)blockIdx.x * kSortChunk;
+    for (int k = 0; k < kSortItems; ++k) {
+        const int64_t i = start + k * kSortThreads + t;
+        const bool valid = i < n;
+        const uint32_t key = valid ? kin[i] : 0u;
+        const uint32_t val = valid ? vin[i] : 0u;
+        const uint32_t d = (key >> shift) & 255u;
+        // Lanes of this wave holding the same digit.
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool set = (d >> bit) & 1u;
+            const uint64_t m = __ballot(set);
+            peers &= set ? m : ~m;
+        }
+        const uint32_t rank = __popcll(peers & lt);
+        const uint32_t wcount = __popcll(peers);
+#pragma unroll
+        for (int j = 0; j < kWaves; ++j) cnt[j][t] = 0;
+        __syncthreads();
+        if (valid && rank == 0) cnt[w][d] = wcount;
+        __syncthreads();
+        if (valid) {
+            uint32_t off = base[d] + rank;
+            for (int j = 0; j < w; ++j) off += cnt[j][d];
+            kout[off] = key;
+            vout[off] = val;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int j = 0; j < kWaves; ++j) add += cnt[j][t];
+        base[t] += add;
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------------------
+// Gathers
+// ----------------------------------------------------------------------------------------
+// One wave per cluster of 64 sorted sources: gather, pack g = w f, cluster bounding sphere.
+__global__ __launch_bounds__(256) void k_gather_src(
+    const uint32_t *__restrict__ order, int64_t n, int64_t np, const double *__restrict__ x,
+    const double *__restrict__ y, const double *__restrict__ z, const double *__restrict__ w,
+    const double *__restrict__ fx, const double *__restrict__ fy, const double *__restrict__ fz,
+    const double *__restrict__ centre, SrcOut o)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // np % 256 == 0
+    const bool real = p < n;
+    const uint32_t idx = order[real ? p : n - 1];
+    const double px = x[idx], py = y[idx], pz = z[idx];
+    const double wt = real ? w[idx] : 0.0;
+    const double gx = wt * fx[idx], gy = wt * fy[idx], gz = wt * fz[idx];
+    o.x[p] = px; o.y[p] = py; o.z[p] = pz;
+    o.gx[p] = gx; o.gy[p] = gy; o.gz[p] = gz;
+    if (o.x32) {
+        o.x32[p] = (float)(px - centre[0]);
+        o.y32[p] = (float)(py - centre[1]);
+        o.z32[p] = (float)(pz - centre[2]);
+        o.gx32[p] = (float)gx; o.gy32[p] = (float)gy; o.gz32[p] = (float)gz;
+    }
+    if (o.perm) o.perm[p] = real ? (int32_t)idx : -1;
+    // Cluster sphere: centre of the cluster's box, radius = farthest member (+ a relative
+    // margin so that rounding never shrinks it).
+    const double cx = 0.5 * (wave_min(px) + wave_max(px));
+    const double cy = 0.5 * (wave_min(py) + wave_max(py));
+    const double cz = 0.5 * (wave_min(pz) + wave_max(pz));
+    const double dx = px - cx, dy = py - cy, dz = pz - cz;
+    const double rad = sqrt(wave_max(dx * dx + dy * dy + dz * dz)) * (1.0 + 0x1p-40);
+    if ((threadIdx.x % kWave) == 0) o.sphere[p / kCluster] = make_double4(cx, cy, cz, rad);
+}
+
+__global__ __launch_bounds__(256) void k_gather_tgt(
+    const uint32_t *__restrict__ order, int64_t n, const double *__restrict__ x,
+    const double *__restrict__ y, const double *__restrict__ z,
+    const double *__restrict__ delta_in, const double *__restrict__ centre, TgtOut o)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool real = p < n;
+    const uint32_t idx = order[real ? p : n - 1];
+    if (o.x) {   // positions (absent when only the per-target delta is gathered)
+        const double px = x[idx], py = y[idx], pz = z[idx];
+        o.x[p] = px; o.y[p] = py; o.z[p] = pz;
+        if (o.x32) {
+            o.x32[p] = (float)(px - centre[0]);
+            o.y32[p] = (float)(py - centre[1]);
+            o.z32[p] = (float)(pz - centre[2]);
+        }
+    }
+    if (o.delta) o.delta[p] = delta_in[idx];
+    if (o.perm) o.perm[p] = real ? (int32_t)idx : -1;
+}
+
+__global__ __launch_bounds__(256) void k_gather_density(
+    const int32_t *__restrict__ perm, int64_t np, const double *__restrict__ w_sorted,
+    const double *__restrict__ fx, const double *__restrict__ fy, const double *__restrict__ fz,
+    double *__restrict__ gx, double *__restrict__ gy, double *__restrict__ gz,
+    float *__restrict__ gx32, float *__restrict__ gy32, float *__restrict__ gz32)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const int32_t idx = perm[p];
+    double a = 0.0, b = 0.0, c = 0.0;
+    if (idx >= 0) {
+        const double wt = w_sorted[p];
+        a = wt * fx[idx]; b = wt * fy[idx]; c = wt * fz[idx];
+    }
+    gx[p] = a; gy[p] = b; gz[p] = c;
+    if (gx32) { gx32[p] = (float)a; gy32[p] = (float)b; gz32[p] = (float)c; }
+}
+
+int sort_blocks(int64_t n) { return (int)((n + kSortChunk - 1) / kSortChunk); }
+
+}  // namespace
+
+// ----------------------------------------------------------------------------------------
+// Host wrappers
+// ----------------------------------------------------------------------------------------
+size_t sort_scratch_bytes(int64_t n)
+{
+    const int64_t nb = sort_blocks(n > 0 ? n : 1);
+    size_t b = 0;
+    b += 4 * round_up(n * 4, 256);                 // keys[2], vals[2]
+    b += round_up(256 * nb * 4, 256);              // counts
+    b += round_up(kBboxBlocks * 6 * 8, 256);       // bbox partials
+    b += 256 + 256;                                // bbox, centre
+    return b;
+}
+
+void carve_sort_scratch(void *base, int64_t n, PackScratch &ps)
+{
+    char *p = static_cast<char *>(base);
+    const int64_t nb = sort_blocks(n > 0 ? n : 1);
+    for (int k = 0; k < 2; ++k) { ps.keys[k] = (uint32_t *)p; p += round_up(n * 4, 256); }
+    for (int k = 0; k < 2; ++k) { ps.vals[k] = (uint32_t *)p; p += round_up(n * 4, 256); }
+    ps.counts = (uint32_t *)p; p += round_up(256 * nb * 4, 256);
+    ps.bbox_part = (double *)p; p += round_up(kBboxBlocks * 6 * 8, 256);
+    ps.bbox = (double *)p; p += 256;
+    ps.centre = (double *)p;
+}
+
+hipError_t launch_bbox(const double *ax, const double *ay, const double *az, int64_t na,
+                       const double *bx, const double *by, const double *bz, int64_t nb,
+                       const PackScratch &ps, hipStream_t st)
+{
+    const int64_t tot = na + nb;
+    int blocks = (int)((tot + kBboxThreads - 1) / kBboxThreads);
+    blocks = blocks < 1 ? 1 : (blocks > kBboxBlocks ? kBboxBlocks : blocks);
+    hipLaunchKernelGGL(k_bbox_partial, dim3(blocks), dim3(kBboxThreads), 0, st, ax, ay, az, na,
+                       bx, by, bz, nb, ps.bbox_part);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kWave), 0, st, ps.bbox_part, blocks, ps.bbox,
+                       ps.centre);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_points(const double *x, const double *y, const double *z, int64_t n,
+                              const PackScratch &ps, const uint32_t **order, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_morton, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, y, z, n,
+                       ps.bbox, ps.keys[0], ps.vals[0]);
+    const int nb = sort_blocks(n);
+    int cur = 0;
+    for (int shift = 0; shift < 3 * kMortonBits; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kSortThreads), 0, st, ps.keys[cur], n, shift,
+                           ps.counts, nb);
+        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, ps.counts, (int64_t)256 * nb);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kSortThreads), 0, st, ps.keys[cur],
+                           ps.vals[cur], ps.keys[cur ^ 1], ps.vals[cur ^ 1], n, shift, ps.counts,
+                           nb);
+        cur ^= 1;
+    }
+    *order = ps.vals[cur];
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_src(const uint32_t *order, int64_t n, int64_t np, const double *x,
+                             const double *y, const double *z, const double *w, const double *fx,
+                             const double *fy, const double *fz, const double *centre,
+                             const SrcOut &o, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gather_src, dim3((unsigned)(np / 256)), dim3(256), 0, st, order, n, np,
+                       x, y, z, w, fx, fy, fz, centre, o);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_tgt(const uint32_t *order, int64_t n, int64_t np, const double *x,
+                             const double *y, const double *z, const double *delta_in,
+                             const double *centre, const TgtOut &o, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gather_tgt, dim3((unsigned)(np / 256)), dim3(256), 0, st, order, n, x, y,
+                       z, delta_in, centre, o);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_density(const int32_t *perm, int64_t n, int64_t np, const double *w,
+                                 const double *fx, const double *fy, const double *fz,
+                                 double *gx, double *gy, double *gz, float *gx32, float *gy32,
+                                 float *gz32, hipStream_t st)
+{
+    (void)n;
+    hipLaunchKernelGGL(k_gather_density, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st,
+                       perm, np, w, fx, fy, fz, gx, gy, gz, gx32, gy32, gz32);
+    return hipGetLastError();
+}
+
+}  // namespace sl

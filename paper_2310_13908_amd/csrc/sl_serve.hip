@@ -1,0 +1,24 @@
+// sl_serve.hip -- resident surfaces and the continuously batched persistent kernel.
+#include "sl_internal.h"
+
+using namespace sl;
+
+extern "C" {
+
+void sl_destroy(sl_ctx *ctx) { delete ctx; }
+
+sl_status sl_surface_register(sl_ctx *, int64_t, const double *, const double *, const double *,
+                              const double *, double, uint64_t *)
+{
+    return fail(SL_EINVAL, "serving not built");
+}
+sl_status sl_surface_release(sl_ctx *, uint64_t) { return fail(SL_EINVAL, "serving not built"); }
+sl_status sl_submit(sl_ctx *, uint64_t, sl_precision, const double *, const double *,
+                    const double *, double, double *, double *, double *, uint64_t *)
+{
+    return fail(SL_EINVAL, "serving not built");
+}
+sl_status sl_poll(sl_ctx *, uint64_t, int *) { return fail(SL_EINVAL, "serving not built"); }
+sl_status sl_wait(sl_ctx *, uint64_t, double) { return fail(SL_EINVAL, "serving not built"); }
+sl_status sl_get_stats(const sl_ctx *, sl_stats *) { return fail(SL_EINVAL, "serving not built"); }
+}

@@ -67,10 +67,22 @@ void sl_destroy(sl_ctx *ctx);
  * valid until the next library call on that thread. */
 const char *sl_last_error(void);
 
-/* Tunables.  SL_PARAM_RHO64: in SL_MIXED, pairs with r/delta below this value are summed in
- * double precision (the single-precision zone needs r/delta >= 5, where s1 = s2 = 1 to single
- * precision; values below 5 are rejected).  Default 5. */
-typedef enum { SL_PARAM_RHO64 = 0 } sl_param;
+/* Tunables.
+ * SL_PARAM_RHO64: in SL_MIXED, pairs with r/delta below this value are summed in double
+ *   precision (the single-precision zone needs r/delta >= 5, where s1 = s2 = 1 to single
+ *   precision; values below 5 are rejected).  Default 5.
+ * SL_PARAM_KERNEL_TIMING: 1 = bracket every pair-kernel launch of sl_eval with HIP events on
+ *   the caller's stream and accumulate the elapsed time into sl_stats; 0 (default) = off.
+ * SL_PARAM_TARGETS_PER_LANE: targets each lane of the pair kernel keeps in registers
+ *   (1, 2 or 4; default 2).
+ * SL_PARAM_WAVES_PER_SIMD: the pair kernel splits the sources until the launch holds about
+ *   this many wavefronts per SIMD (1..32; default 4). */
+typedef enum {
+    SL_PARAM_RHO64 = 0,
+    SL_PARAM_KERNEL_TIMING = 1,
+    SL_PARAM_TARGETS_PER_LANE = 2,
+    SL_PARAM_WAVES_PER_SIMD = 3
+} sl_param;
 sl_status sl_set_param(sl_ctx *ctx, sl_param key, double value);
 sl_status sl_get_param(const sl_ctx *ctx, sl_param key, double *value);
 
@@ -133,15 +145,19 @@ sl_status sl_submit(sl_ctx *ctx, uint64_t handle, sl_precision prec,
 sl_status sl_poll(sl_ctx *ctx, uint64_t request, int *done);
 sl_status sl_wait(sl_ctx *ctx, uint64_t request, double timeout_s);
 
-/* Serving statistics since sl_create (for reporting): requests completed, work items
- * executed, persistent-kernel launches, bytes currently admitted. */
+/* Statistics since sl_create (for reporting): serving requests completed, work items
+ * executed, persistent-kernel launches, bytes currently admitted; and, while
+ * SL_PARAM_KERNEL_TIMING is on, the number of timed sl_eval pair-kernel launches and their
+ * summed duration.  Waits for the timed launches to finish. */
 typedef struct {
     uint64_t requests_done;
     uint64_t items_done;
     uint64_t kernel_launches;
     uint64_t bytes_admitted;
+    uint64_t pair_launches;
+    double pair_ms;
 } sl_stats;
-sl_status sl_get_stats(const sl_ctx *ctx, sl_stats *out);
+sl_status sl_get_stats(sl_ctx *ctx, sl_stats *out);
 
 #ifdef __cplusplus
 }

@@ -14,6 +14,9 @@ LIB_PATH = os.path.join(_PKG, "libstokeslet.so")
 SL_OK, SL_EINVAL, SL_ENOMEM, SL_EBUSY, SL_EHIP, SL_ENOTFOUND, SL_ETIMEDOUT = 0, -1, -2, -3, -4, -5, -6
 SL_FP64, SL_MIXED = 0, 1
 SL_PARAM_RHO64 = 0
+SL_PARAM_KERNEL_TIMING = 1
+SL_PARAM_TARGETS_PER_LANE = 2
+SL_PARAM_WAVES_PER_SIMD = 3
 
 STATUS_NAMES = {0: "SL_OK", -1: "SL_EINVAL", -2: "SL_ENOMEM", -3: "SL_EBUSY", -4: "SL_EHIP",
                 -5: "SL_ENOTFOUND", -6: "SL_ETIMEDOUT"}
@@ -32,7 +35,8 @@ class SlError(RuntimeError):
 
 class sl_stats(ctypes.Structure):
     _fields_ = [("requests_done", ctypes.c_uint64), ("items_done", ctypes.c_uint64),
-                ("kernel_launches", ctypes.c_uint64), ("bytes_admitted", ctypes.c_uint64)]
+                ("kernel_launches", ctypes.c_uint64), ("bytes_admitted", ctypes.c_uint64),
+                ("pair_launches", ctypes.c_uint64), ("pair_ms", ctypes.c_double)]
 
 
 _lib = None

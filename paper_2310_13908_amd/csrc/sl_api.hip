@@ -41,8 +41,6 @@ bool overlaps(const Range &a, const Range &b)
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
 constexpr int64_t kMaxPoints = (int64_t)1 << 30;
-constexpr int kTargetsPerLane = 2;
-constexpr int kWavesPerSimd = 4;
 
 }  // namespace
 
@@ -141,6 +139,26 @@ sl_status sl_set_param(sl_ctx *ctx, sl_param key, double value)
         ctx->rho64 = value;
         return SL_OK;
     }
+    if (key == SL_PARAM_TARGETS_PER_LANE) {
+        if (value != 1.0 && value != 2.0 && value != 4.0)
+            return fail(SL_EINVAL, "sl_set_param: targets per lane is 1, 2 or 4");
+        std::lock_guard<std::mutex> l(ctx->mu);
+        ctx->targets_per_lane = (int)value;
+        return SL_OK;
+    }
+    if (key == SL_PARAM_WAVES_PER_SIMD) {
+        if (!(value >= 1.0 && value <= 32.0) || value != (double)(int)value)
+            return fail(SL_EINVAL, "sl_set_param: waves per SIMD is an integer in 1..32");
+        std::lock_guard<std::mutex> l(ctx->mu);
+        ctx->waves_per_simd = (int)value;
+        return SL_OK;
+    }
+    if (key == SL_PARAM_KERNEL_TIMING) {
+        if (value != 0.0 && value != 1.0) return fail(SL_EINVAL, "sl_set_param: timing is 0 or 1");
+        std::lock_guard<std::mutex> l(ctx->mu);
+        ctx->timing = value == 1.0;
+        return SL_OK;
+    }
     return fail(SL_EINVAL, "sl_set_param: unknown key");
 }
 
@@ -151,7 +169,43 @@ sl_status sl_get_param(const sl_ctx *ctx, sl_param key, double *value)
         *value = ctx->rho64;
         return SL_OK;
     }
+    if (key == SL_PARAM_KERNEL_TIMING) {
+        *value = ctx->timing ? 1.0 : 0.0;
+        return SL_OK;
+    }
+    if (key == SL_PARAM_TARGETS_PER_LANE) {
+        *value = ctx->targets_per_lane;
+        return SL_OK;
+    }
+    if (key == SL_PARAM_WAVES_PER_SIMD) {
+        *value = ctx->waves_per_simd;
+        return SL_OK;
+    }
     return fail(SL_EINVAL, "sl_get_param: unknown key");
+}
+
+sl_status sl_get_stats(sl_ctx *ctx, sl_stats *out)
+{
+    if (!ctx || !out) return fail(SL_EINVAL, "sl_get_stats: NULL argument");
+    memset(out, 0, sizeof(*out));
+    {
+        std::lock_guard<std::mutex> l(ctx->mu);
+        DeviceGuard g(ctx->device);
+        for (auto &ev : ctx->timed) {
+            float ms = 0.0f;
+            SL_HIP(hipEventSynchronize(ev.second));
+            SL_HIP(hipEventElapsedTime(&ms, ev.first, ev.second));
+            ctx->pair_ms += ms;
+            ctx->pair_launches += 1;
+            ctx->spare_events.push_back(ev.first);
+            ctx->spare_events.push_back(ev.second);
+        }
+        ctx->timed.clear();
+        out->pair_launches = ctx->pair_launches;
+        out->pair_ms = ctx->pair_ms;
+    }
+    server_stats(ctx, out);
+    return SL_OK;
 }
 
 sl_status sl_eval(sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *sx,
@@ -200,7 +254,13 @@ sl_status sl_eval(sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *s
     const int64_t np_s = round_up(n_src, kPad);
     const int64_t np_t = same ? np_s : round_up(n_tgt, kPad);
     const int64_t n_sort = std::max(n_src, same ? (int64_t)0 : n_tgt);
-    const PairPlan plan = plan_pairs(np_s, np_t, kTargetsPerLane, ctx->n_cu * 4 * kWavesPerSimd);
+    int R, wps;
+    {
+        std::lock_guard<std::mutex> l(ctx->mu);
+        R = ctx->targets_per_lane;
+        wps = ctx->waves_per_simd;
+    }
+    const PairPlan plan = plan_pairs(np_s, np_t, R, ctx->n_cu * 4 * wps);
 
     EvalWorkspace ws;
     const size_t bytes = carve(nullptr, ws, n_sort, np_s, np_t, !same, mixed, vard, plan.n_splits);
@@ -248,7 +308,25 @@ sl_status sl_eval(sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *s
     pa.n_tblocks = plan.n_tblocks;
     pa.part = ws.part;
     pa.bbox = ws.ps.bbox;
+    std::pair<hipEvent_t, hipEvent_t> tev{nullptr, nullptr};
+    if (ctx->timing && e == hipSuccess) {
+        std::lock_guard<std::mutex> l(ctx->mu);
+        for (hipEvent_t *ev : {&tev.first, &tev.second}) {
+            if (!ctx->spare_events.empty()) {
+                *ev = ctx->spare_events.back();
+                ctx->spare_events.pop_back();
+            } else if (e == hipSuccess) {
+                e = hipEventCreate(ev);
+            }
+        }
+        if (e == hipSuccess) e = hipEventRecord(tev.first, st);
+    }
     if (e == hipSuccess) e = launch_pair(pa, plan, mixed, vard, st);
+    if (tev.second && e == hipSuccess) {
+        e = hipEventRecord(tev.second, st);
+        std::lock_guard<std::mutex> l(ctx->mu);
+        if (e == hipSuccess) ctx->timed.push_back(tev);
+    }
     if (e == hipSuccess)
         e = launch_reduce(ws.part, plan.n_splits, np_t, tv.perm, 1.0 / (8.0 * M_PI * mu), ux, uy, uz, st);
     const hipError_t ef = hipFreeAsync(base, st);

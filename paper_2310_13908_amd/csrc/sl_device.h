@@ -7,19 +7,15 @@
 //
 // Far from the target (r/delta >= 6.9) both smoothing factors equal 1 to double precision
 // (|s - 1| < 2^-53; at r/delta >= 5, |s - 1| < 2^-24), so the far pair is the plain
-// Stokeslet K1 = 1/r, K2 = 1/r^3: 28 flops, no erf/exp.  Near the target the smoothing is
-// applied in double precision, written without divisions:
-//
-//     q = (r/delta)^2,  E = exp(-q),  a = (2/(3 sqrt(pi))) E / delta,
-//     K1 = erf(r/delta)/r - a (2q - 5),
-//     K2 = erf(r/delta)/r^3 - a ( (4q - 14)/delta^2 + 3/r^2 ),
-//
-// which is s1/r and s2/r^3 of Sec. 3.4 expanded; at r = 0 the limit K1 = 16/(3 delta sqrt(pi))
-// of Sec. 3.4 is used (the K2 term carries d twice and vanishes).
+// Stokeslet K1 = 1/r, K2 = 1/r^3: 28 flops, no erf/exp.  Nearer pairs apply the smoothing in
+// double precision (smoothing64 below: a power series near r = 0, otherwise one exp and a
+// fitted scaled complementary error function).
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "sl_smoothing_coeffs.h"
 
 namespace sl {
 
@@ -58,10 +54,10 @@ __device__ __forceinline__ void far_pair64(double tx, double ty, double tz,
     az = fma(ri, fma(c, dz, gz), az);
 }
 
-// Per-target constants of the smoothing: 1/delta, 1/delta^2, a0 = 2/(3 sqrt(pi) delta) and
-// the squared radius inside which the smoothing differs from 1 in double precision.
+// Per-target constants of the smoothing: powers of 1/delta and the squared radius inside
+// which the smoothing differs from 1 in double precision.
 struct DeltaC {
-    double id, id2, a0, cut2;
+    double id, id2, id3, cut2;
 };
 
 __device__ __forceinline__ DeltaC make_delta(double delta)
@@ -69,10 +65,74 @@ __device__ __forceinline__ DeltaC make_delta(double delta)
     DeltaC c;
     c.id = 1.0 / delta;
     c.id2 = c.id * c.id;
-    c.a0 = kC0 * c.id;
+    c.id3 = c.id2 * c.id;
     const double rc = kRhoExact64 * delta;
     c.cut2 = rc * rc;
     return c;
+}
+
+// A polynomial coefficient placed in a scalar register where it is used.  Without this the
+// compiler hoists the ~60 double constants of the smoothing out of the source loop into vector
+// registers, which costs more than a hundred VGPRs and halves the occupancy; rematerializing
+// them with scalar moves keeps them off the vector register file.
+__device__ __forceinline__ double sconst(double c)
+{
+    asm volatile("" : "+s"(c));
+    return c;
+}
+
+// e^{-q} for 0 <= q <= 700: q = n ln2 + f with |f| <= ln2/2, e^{-q} = 2^-n e^{-f}, e^{-f} by
+// its Taylor series (degree 13: truncation below 2^-53 relative).
+__device__ __forceinline__ double exp_neg64(double q)
+{
+    const double n = rint(q * kLog2E);
+    const double f = fma(-n, kLn2Lo, fma(-n, kLn2Hi, q));
+    double p = kExpC[kExpDeg];
+#pragma unroll
+    for (int k = kExpDeg - 1; k >= 0; --k) p = fma(p, -f, sconst(kExpC[k]));
+    return ldexp(p, -(int)n);
+}
+
+// Smoothed kernel factors K1 = s1(p)/r, K2 = s2(p)/r^3 for p = r/delta < 6.9 (Sec. 3.4), given
+// r2 = r^2 and ri = 1/r (ri is not used when r = 0).
+//   p^2 < 0.25: K1 = F1(p^2)/delta, K2 = F2(p^2)/delta^3 with the power series of s1/p and s2/p^3
+//               (no cancellation, and the r = 0 limits 16/(3 sqrt(pi) delta), 32/(3 sqrt(pi)
+//               delta^3) come out at q = 0);
+//   otherwise:  s = 1 - e^{-q} (g(p) + P(p)), g(p) = e^{p^2} erfc(p) from its fitted polynomial
+//               in t = 3/(3+p), P1 = (2/(3 sqrt(pi))) p (2q - 5),
+//               P2 = (2/(3 sqrt(pi))) p (4q^2 - 14q + 3).
+__device__ __forceinline__ void smoothing64(double r2, double ri, double ri2, const DeltaC &dc,
+                                            double &K1, double &K2)
+{
+    const double q = r2 * dc.id2;
+    if (q < kSeriesQMax) {
+        double f1 = kF1[kSeriesTerms - 1], f2 = kF2[kSeriesTerms - 1];
+#pragma unroll
+        for (int k = kSeriesTerms - 2; k >= 0; --k) {
+            f1 = fma(f1, q, sconst(kF1[k]));
+            f2 = fma(f2, q, sconst(kF2[k]));
+        }
+        K1 = f1 * dc.id;
+        K2 = f2 * dc.id3;
+    } else {
+        const double p = (r2 * ri) * dc.id;
+        const double E = exp_neg64(q);
+        const double den = kGK + p;
+        double y = __builtin_amdgcn_rcp(den);      // refined twice: 1/den to ~1 ulp
+        double e = fma(-den, y, 1.0);
+        y = fma(y, e, y);
+        e = fma(-den, y, 1.0);
+        y = fma(y, e, y);
+        const double t = kGK * y;
+        double g = kG[kGDeg];
+#pragma unroll
+        for (int i = kGDeg - 1; i >= 0; --i) g = fma(g, t, sconst(kG[i]));
+        const double c0p = kC0 * p;
+        const double A1 = fma(c0p, fma(2.0, q, -5.0), g);
+        const double A2 = fma(c0p, fma(q, fma(4.0, q, -14.0), 3.0), g);
+        K1 = ri * fma(-E, A1, 1.0);
+        K2 = (ri * ri2) * fma(-E, A2, 1.0);
+    }
 }
 
 // Regularized pair in double precision: the exact kernel for any r >= 0.
@@ -84,22 +144,10 @@ __device__ __forceinline__ void near_pair64(double tx, double ty, double tz,
 {
     const double dx = tx - sx, dy = ty - sy, dz = tz - sz;
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    const bool pos = r2 > 0.0;
-    const double ri = rsqrt64(pos ? r2 : 1.0);
+    const double ri = rsqrt64(r2 > 0.0 ? r2 : 1.0);
     const double ri2 = ri * ri;
     double K1 = ri, K2 = ri * ri2;
-    if (r2 < dc.cut2) {
-        const double q = r2 * dc.id2;
-        const double rho = (r2 * ri) * dc.id;
-        const double a = dc.a0 * exp(-q);
-        const double er = erf(rho);
-        K1 = fma(-a, fma(2.0, q, -5.0), er * ri);
-        K2 = fma(-a, fma(dc.id2, fma(4.0, q, -14.0), 3.0 * ri2), er * ri * ri2);
-        if (!pos) {
-            K1 = 8.0 * dc.a0;       // 16 / (3 sqrt(pi) delta)
-            K2 = 0.0;
-        }
-    }
+    if (r2 < dc.cut2) smoothing64(r2, ri, ri2, dc, K1, K2);
     const double gd = fma(gx, dx, fma(gy, dy, gz * dz));
     const double c = gd * K2;
     ax = fma(K1, gx, fma(c, dx, ax));

@@ -142,8 +142,11 @@ hipError_t launch_gather_density(const int32_t *perm, int64_t n, int64_t np, con
 // ---------------------------------------------------------------------------------------
 // Context
 // ---------------------------------------------------------------------------------------
+struct sl_ctx;
 namespace sl {
 struct Server;   // serving runtime (sl_serve.hip)
+// Fills the serving fields of `out` (zeros when the context never served).
+void server_stats(sl_ctx *ctx, sl_stats *out);
 }
 
 struct sl_ctx {
@@ -151,6 +154,14 @@ struct sl_ctx {
     int n_cu = 0;
     size_t budget = 0;
     double rho64 = sl::kRhoExact32;
+    int targets_per_lane = 2;
+    int waves_per_simd = 4;
     std::mutex mu;
     sl::Server *server = nullptr;
+    // pair-kernel timing (SL_PARAM_KERNEL_TIMING)
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;   // recorded, not yet read
+    std::vector<hipEvent_t> spare_events;
+    uint64_t pair_launches = 0;
+    double pair_ms = 0.0;
 };

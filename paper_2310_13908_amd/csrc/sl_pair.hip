@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kWave) void k_pair(PairArgs a)
                 }
             }
         } else {
-#pragma unroll 2
+#pragma unroll 1
             for (int j = 0; j < kCluster; ++j) {
                 const double sx = a.s.x[j0 + j], sy = a.s.y[j0 + j], sz = a.s.z[j0 + j];
                 const double gx = a.s.gx[j0 + j], gy = a.s.gy[j0 + j], gz = a.s.gz[j0 + j];

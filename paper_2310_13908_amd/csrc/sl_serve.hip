@@ -3,9 +3,17 @@
 
 using namespace sl;
 
+void sl::server_stats(sl_ctx *, sl_stats *) {}
+
 extern "C" {
 
-void sl_destroy(sl_ctx *ctx) { delete ctx; }
+void sl_destroy(sl_ctx *ctx)
+{
+    if (!ctx) return;
+    for (auto &ev : ctx->timed) { (void)hipEventDestroy(ev.first); (void)hipEventDestroy(ev.second); }
+    for (auto ev : ctx->spare_events) (void)hipEventDestroy(ev);
+    delete ctx;
+}
 
 sl_status sl_surface_register(sl_ctx *, int64_t, const double *, const double *, const double *,
                               const double *, double, uint64_t *)
@@ -20,5 +28,4 @@ sl_status sl_submit(sl_ctx *, uint64_t, sl_precision, const double *, const doub
 }
 sl_status sl_poll(sl_ctx *, uint64_t, int *) { return fail(SL_EINVAL, "serving not built"); }
 sl_status sl_wait(sl_ctx *, uint64_t, double) { return fail(SL_EINVAL, "serving not built"); }
-sl_status sl_get_stats(const sl_ctx *, sl_stats *) { return fail(SL_EINVAL, "serving not built"); }
 }

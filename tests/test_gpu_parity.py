@@ -127,6 +127,29 @@ def test_per_target_delta(ctx, precision):
     assert eps(u, ref) < TOL[precision]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_smoothing_profile_single_source(ctx, precision):
+    """One source, targets at r/delta from 0 (coincident) through the series/fit switch (0.5)
+    and the exact-smoothing cut (6.9) to 9, in many directions: every target's velocity is a
+    single pair term, so this checks the device s1/r and s2/r^3 per target, not in a norm."""
+    import oracle
+    rng = np.random.default_rng(17)
+    delta = 0.037
+    rho = np.concatenate([[0.0, 1e-12, 1e-8, 1e-5, 1e-3, 0.1, 0.4999, 0.5, 0.5001],
+                          np.linspace(0.0, 9.0, 1801)[1:], [4.9999, 5.0, 5.0001, 6.8999, 6.9, 6.9001]])
+    dirs = rng.standard_normal((rho.size, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    src = np.array([[0.31, -0.72, 0.18]])
+    T = src + rho[:, None] * delta * dirs
+    g = np.array([[0.8, -1.3, 0.45]])
+    u = gpu_eval(ctx, src, [0.02], g, delta, targets=T, precision=precision)
+    ref = oracle.single_layer(src, [0.02], g, delta, targets=T)
+    rel = np.linalg.norm(u - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    # double precision everywhere below r/delta = 5 in both modes; single precision beyond in mixed
+    tol = np.where(rho < 5.0, 2e-14, 2e-14 if precision == "fp64" else 1e-6)
+    assert np.all(rel <= tol), (rho[rel > tol][:5], rel[rel > tol][:5])
+
+
 def test_degenerate_sizes(ctx):
     import torch
     import oracle

@@ -62,6 +62,7 @@ struct EvalWorkspace {
     SrcOut so;
     TgtOut to;
     double *part;
+    void *tblock;
 };
 
 static size_t carve(char *base, EvalWorkspace &w, int64_t n_sort, int64_t np_s, int64_t np_t,
@@ -94,6 +95,7 @@ static size_t carve(char *base, EvalWorkspace &w, int64_t n_sort, int64_t np_s, 
     }
     if (vard) w.to.delta = (double *)take(np_t * 8);
     w.part = (double *)take((size_t)n_splits * 3 * np_t * 8);
+    w.tblock = take(tblock_scratch_bytes((int)(np_t / kWave)));   // enough for any R >= 1
     return off;
 }
 
@@ -192,17 +194,20 @@ sl_status sl_get_stats(sl_ctx *ctx, sl_stats *out)
         std::lock_guard<std::mutex> l(ctx->mu);
         DeviceGuard g(ctx->device);
         for (auto &ev : ctx->timed) {
-            float ms = 0.0f;
-            SL_HIP(hipEventSynchronize(ev.second));
-            SL_HIP(hipEventElapsedTime(&ms, ev.first, ev.second));
-            ctx->pair_ms += ms;
+            float ms_far = 0.0f, ms_near = 0.0f;
+            SL_HIP(hipEventSynchronize(ev.e2));
+            SL_HIP(hipEventElapsedTime(&ms_far, ev.e0, ev.e1));
+            SL_HIP(hipEventElapsedTime(&ms_near, ev.e1, ev.e2));
+            ctx->far_ms += ms_far;
+            ctx->near_ms += ms_near;
             ctx->pair_launches += 1;
-            ctx->spare_events.push_back(ev.first);
-            ctx->spare_events.push_back(ev.second);
+            for (hipEvent_t e : {ev.e0, ev.e1, ev.e2}) ctx->spare_events.push_back(e);
         }
         ctx->timed.clear();
         out->pair_launches = ctx->pair_launches;
-        out->pair_ms = ctx->pair_ms;
+        out->pair_ms = ctx->far_ms + ctx->near_ms;
+        out->far_ms = ctx->far_ms;
+        out->near_ms = ctx->near_ms;
     }
     server_stats(ctx, out);
     return SL_OK;
@@ -308,10 +313,11 @@ sl_status sl_eval(sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *s
     pa.n_tblocks = plan.n_tblocks;
     pa.part = ws.part;
     pa.bbox = ws.ps.bbox;
-    std::pair<hipEvent_t, hipEvent_t> tev{nullptr, nullptr};
+    pa.tblock_scratch = ws.tblock;
+    PairTiming tev{nullptr, nullptr, nullptr};
     if (ctx->timing && e == hipSuccess) {
         std::lock_guard<std::mutex> l(ctx->mu);
-        for (hipEvent_t *ev : {&tev.first, &tev.second}) {
+        for (hipEvent_t *ev : {&tev.e0, &tev.e1, &tev.e2}) {
             if (!ctx->spare_events.empty()) {
                 *ev = ctx->spare_events.back();
                 ctx->spare_events.pop_back();
@@ -319,13 +325,11 @@ sl_status sl_eval(sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *s
                 e = hipEventCreate(ev);
             }
         }
-        if (e == hipSuccess) e = hipEventRecord(tev.first, st);
     }
-    if (e == hipSuccess) e = launch_pair(pa, plan, mixed, vard, st);
-    if (tev.second && e == hipSuccess) {
-        e = hipEventRecord(tev.second, st);
+    if (e == hipSuccess) e = launch_pair(pa, plan, mixed, vard, st, tev.e2 ? &tev : nullptr);
+    if (tev.e2 && e == hipSuccess) {
         std::lock_guard<std::mutex> l(ctx->mu);
-        if (e == hipSuccess) ctx->timed.push_back(tev);
+        ctx->timed.push_back(tev);
     }
     if (e == hipSuccess)
         e = launch_reduce(ws.part, plan.n_splits, np_t, tv.perm, 1.0 / (8.0 * M_PI * mu), ux, uy, uz, st);

@@ -182,6 +182,27 @@ __device__ __forceinline__ void two_sum_acc(float s, float &hi, float &lo)
     lo += e;
 }
 
+// Per target block: bounding-sphere centre and radius and the far threshold cut * delta_max
+// (the serving path keeps one threshold per precision in gap_far / gap_far_mixed).
+struct TBlockRec {
+    double cx, cy, cz, rad, gap_far, gap_far_mixed, pad0, pad1;
+};
+
+// Classification of a source cluster (bounding sphere S) against a target block: far when the
+// gap between the spheres is at least `gap_far`.  Written with explicit fused operations only,
+// so that every kernel that inlines it computes bit-identical gaps.
+__device__ __forceinline__ bool cluster_is_far(const TBlockRec &tb, const double4 &S, double gap_far)
+{
+    const double ex = tb.cx - S.x, ey = tb.cy - S.y, ez = tb.cz - S.z;
+    const double d2 = fma(ex, ex, fma(ey, ey, __dmul_rn(ez, ez)));
+    const double gap = __dsub_rn(__dsub_rn(sqrt(d2), tb.rad), S.w);
+    return gap >= gap_far;
+}
+__device__ __forceinline__ bool cluster_is_far(const TBlockRec &tb, const double4 &S)
+{
+    return cluster_is_far(tb, S, tb.gap_far);
+}
+
 // Wave-wide reductions (all 64 lanes active).
 __device__ __forceinline__ double wave_min(double v)
 {

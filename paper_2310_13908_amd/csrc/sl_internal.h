@@ -68,7 +68,14 @@ struct PairArgs {
     double *part;            // [n_splits][3][t.np] partial sums (unscaled)
     const double *bbox;      // [6] box of all points (min xyz, max xyz): bounds the rounding
                              // of the single-precision positions in the mixed path
+    void *tblock_scratch;    // tblock_scratch_bytes(n_tblocks): per-target-block spheres
 };
+
+// Optional events recorded around the far kernel (e0 .. e1) and the near kernel (e1 .. e2).
+struct PairTiming {
+    hipEvent_t e0, e1, e2;
+};
+size_t tblock_scratch_bytes(int n_tblocks);
 
 // Launch configuration chosen by the host for a given problem.
 struct PairPlan {
@@ -81,7 +88,7 @@ struct PairPlan {
 PairPlan plan_pairs(int64_t np_src, int64_t np_tgt, int R, int waves_wanted);
 
 hipError_t launch_pair(const PairArgs &a, const PairPlan &p, bool mixed, bool var_delta,
-                       hipStream_t st);
+                       hipStream_t st, const PairTiming *tm);
 hipError_t launch_reduce(const double *part, int n_splits, int64_t np, const int32_t *perm,
                          double scale, double *ux, double *uy, double *uz, hipStream_t st);
 hipError_t launch_fill_zero(double *ux, double *uy, double *uz, int64_t n, hipStream_t st);
@@ -160,8 +167,8 @@ struct sl_ctx {
     sl::Server *server = nullptr;
     // pair-kernel timing (SL_PARAM_KERNEL_TIMING)
     bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;   // recorded, not yet read
+    std::vector<sl::PairTiming> timed;   // recorded, not yet read
     std::vector<hipEvent_t> spare_events;
     uint64_t pair_launches = 0;
-    double pair_ms = 0.0;
+    double far_ms = 0.0, near_ms = 0.0;
 };

@@ -6,16 +6,23 @@
 // Source data are wave-uniform: every lane needs the same source at the same time, so the
 // sources are read with scalar loads into scalar registers straight from L2 -- no LDS
 // staging, no barriers, and every VALU instruction takes the source as a scalar operand.
-// Per cluster of 64 sources the wave tests its bounding sphere against the target block's
-// sphere (a uniform branch):
-//   far  (gap >= cut * delta_max): plain Stokeslet, 28 flops a pair, no erf/exp.
-//        FP64 path: double precision.  Mixed path: single precision, summed per cluster and
-//        folded into a per-target two-sum (hi, lo) pair.
-//   near: regularized kernel in double precision for every pair of the cluster; the
-//        erf/exp smoothing runs only in lanes whose pair is within 6.9 delta.
-// The FP64 far cut is 6.9 (s = 1 to double precision), the mixed one rho64 >= 5 (s = 1 to
-// single precision).  Splits write unscaled partial sums; k_reduce adds them in a fixed
-// order, scales by 1/(8 pi mu) and scatters to the caller's target order.
+//
+// Each (target block, source cluster) pair is classified once by the bounding spheres:
+//   far  (gap >= cut * delta_max): plain Stokeslet, 28 flops a pair, no erf/exp;
+//   near: regularized kernel in double precision.
+// Far and near clusters run in two kernels so that the far kernel -- the bulk of the work at
+// large N -- carries none of the registers of the smoothing code and keeps a high occupancy:
+//   k_tblock: per target block, bounding sphere and far threshold (read by both kernels, so
+//             both classify every cluster from the same numbers);
+//   k_far:    far clusters; FP64 path in double precision, mixed path in single precision
+//             summed per cluster and folded into a per-target two-sum (hi, lo) pair;
+//   k_near:   near clusters in double precision, added onto k_far's partial sums (same
+//             stream, so the order of the additions is fixed);
+//   k_reduce: adds the per-split partials in split order, scales by 1/(8 pi mu) and scatters
+//             to the caller's target order.
+// The FP64 far cut is 6.9 delta (s = 1 to double precision), the mixed one rho64 >= 5 (s = 1 to
+// single precision), widened to 2^-10 box sizes so that single-precision distances stay exact
+// enough.
 #include "sl_internal.h"
 
 namespace sl {
@@ -24,116 +31,117 @@ namespace {
 
 constexpr int kMinClustersPerSplit = 4;
 
-template <int R, bool MIXED, bool VARD>
-__global__ __launch_bounds__(kWave) void k_pair(PairArgs a)
+template <int R>
+__global__ __launch_bounds__(kWave) void k_tblock(PairArgs a, TBlockRec *__restrict__ out,
+                                                  int mixed)
+{
+    const int tb = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t t0 = (int64_t)tb * (kWave * R);
+    double x[R], y[R], z[R];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double dmax = a.delta;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = t0 + r * kWave + lane;
+        x[r] = a.t.x[i];
+        y[r] = a.t.y[i];
+        z[r] = a.t.z[i];
+        if (a.t.delta) dmax = r == 0 ? a.t.delta[i] : fmax(dmax, a.t.delta[i]);
+        lo[0] = fmin(lo[0], x[r]); hi[0] = fmax(hi[0], x[r]);
+        lo[1] = fmin(lo[1], y[r]); hi[1] = fmax(hi[1], y[r]);
+        lo[2] = fmin(lo[2], z[r]); hi[2] = fmax(hi[2], z[r]);
+    }
+    const double cx = 0.5 * (wave_min(lo[0]) + wave_max(hi[0]));
+    const double cy = 0.5 * (wave_min(lo[1]) + wave_max(hi[1]));
+    const double cz = 0.5 * (wave_min(lo[2]) + wave_max(hi[2]));
+    double rr = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double dx = x[r] - cx, dy = y[r] - cy, dz = z[r] - cz;
+        rr = fmax(rr, fma(dx, dx, fma(dy, dy, __dmul_rn(dz, dz))));
+    }
+    rr = wave_max(rr);
+    dmax = wave_max(dmax);
+    if (lane == 0) {
+        double gap_far = a.far_cut * dmax;
+        if (mixed) {
+            const double bx = a.bbox[3] - a.bbox[0], by = a.bbox[4] - a.bbox[1],
+                         bz = a.bbox[5] - a.bbox[2];
+            gap_far = fmax(gap_far, 0x1p-10 * sqrt(fma(bx, bx, fma(by, by, __dmul_rn(bz, bz)))));
+        }
+        TBlockRec rec;
+        rec.cx = cx; rec.cy = cy; rec.cz = cz;
+        rec.rad = sqrt(rr) * (1.0 + 0x1p-40);
+        rec.gap_far = gap_far;
+        rec.gap_far_mixed = gap_far;
+        rec.pad0 = rec.pad1 = 0.0;
+        out[tb] = rec;
+    }
+}
+
+template <int R, bool MIXED>
+__global__ __launch_bounds__(kWave) void k_far(PairArgs a, const TBlockRec *__restrict__ tbr)
 {
     const int split = (int)(blockIdx.x % (unsigned)a.n_splits);
     const int tb = (int)(blockIdx.x / (unsigned)a.n_splits);
     const int lane = threadIdx.x;
     const int64_t t0 = (int64_t)tb * (kWave * R);
     const int64_t np_t = a.t.np;
+    const TBlockRec rec = tbr[tb];
 
     double tx[R], ty[R], tz[R];
     float tx32[R], ty32[R], tz32[R];
-    DeltaC dcv[R];
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    double dmax = a.delta;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t i = t0 + r * kWave + lane;
-        tx[r] = a.t.x[i];
-        ty[r] = a.t.y[i];
-        tz[r] = a.t.z[i];
-        if constexpr (MIXED) {
-            tx32[r] = a.t.x32[i];
-            ty32[r] = a.t.y32[i];
-            tz32[r] = a.t.z32[i];
-        }
-        if constexpr (VARD) {
-            const double d = a.t.delta[i];
-            dcv[r] = make_delta(d);
-            dmax = r == 0 ? d : fmax(dmax, d);
-        }
-        lo[0] = fmin(lo[0], tx[r]); hi[0] = fmax(hi[0], tx[r]);
-        lo[1] = fmin(lo[1], ty[r]); hi[1] = fmax(hi[1], ty[r]);
-        lo[2] = fmin(lo[2], tz[r]); hi[2] = fmax(hi[2], tz[r]);
-    }
-    // Target-block bounding sphere and largest delta, made wave-uniform.
-    const double cx = uniform(0.5 * (wave_min(lo[0]) + wave_max(hi[0])));
-    const double cy = uniform(0.5 * (wave_min(lo[1]) + wave_max(hi[1])));
-    const double cz = uniform(0.5 * (wave_min(lo[2]) + wave_max(hi[2])));
-    double rr = 0.0;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const double dx = tx[r] - cx, dy = ty[r] - cy, dz = tz[r] - cz;
-        rr = fmax(rr, dx * dx + dy * dy + dz * dz);
-    }
-    const double trad = uniform(sqrt(wave_max(rr)) * (1.0 + 0x1p-40));
-    if constexpr (VARD) dmax = uniform(wave_max(dmax));
-    double gap_far = a.far_cut * dmax;
-    if constexpr (MIXED) {
-        // Single-precision positions carry an absolute error of about 2^-24 times the box
-        // size; keep pairs closer than 2^-10 box sizes in double precision so that the
-        // single-precision distance stays accurate (and never rounds to zero).
-        const double bx = a.bbox[3] - a.bbox[0], by = a.bbox[4] - a.bbox[1], bz = a.bbox[5] - a.bbox[2];
-        gap_far = fmax(gap_far, 0x1p-10 * sqrt(bx * bx + by * by + bz * bz));
-    }
-    const DeltaC dcu = make_delta(a.delta);
-
     double ax[R], ay[R], az[R];
     float hx[R], hy[R], hz[R], lx[R], ly[R], lz[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        ax[r] = ay[r] = az[r] = 0.0;
-        hx[r] = hy[r] = hz[r] = lx[r] = ly[r] = lz[r] = 0.0f;
+        const int64_t i = t0 + r * kWave + lane;
+        if constexpr (MIXED) {
+            tx32[r] = a.t.x32[i];
+            ty32[r] = a.t.y32[i];
+            tz32[r] = a.t.z32[i];
+            hx[r] = hy[r] = hz[r] = lx[r] = ly[r] = lz[r] = 0.0f;
+        } else {
+            tx[r] = a.t.x[i];
+            ty[r] = a.t.y[i];
+            tz[r] = a.t.z[i];
+            ax[r] = ay[r] = az[r] = 0.0;
+        }
     }
 
     const int64_t n_cl = a.s.np / kCluster;
     const int64_t c_begin = (int64_t)split * a.clusters_per_split;
     const int64_t c_end = c_begin + a.clusters_per_split < n_cl ? c_begin + a.clusters_per_split : n_cl;
     for (int64_t c = c_begin; c < c_end; ++c) {
-        const double4 S = a.s.sphere[c];
-        const double ex = cx - S.x, ey = cy - S.y, ez = cz - S.z;
-        const double gap = sqrt(ex * ex + ey * ey + ez * ez) - trad - S.w;
+        if (!cluster_is_far(rec, a.s.sphere[c])) continue;
         const int64_t j0 = c * kCluster;
-        if (gap >= gap_far) {
-            if constexpr (MIXED) {
-                float px[R], py[R], pz[R];
+        if constexpr (MIXED) {
+            float px[R], py[R], pz[R];
 #pragma unroll
-                for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
+            for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
 #pragma unroll 8
-                for (int j = 0; j < kCluster; ++j) {
-                    const float sx = a.s.x32[j0 + j], sy = a.s.y32[j0 + j], sz = a.s.z32[j0 + j];
-                    const float gx = a.s.gx32[j0 + j], gy = a.s.gy32[j0 + j], gz = a.s.gz32[j0 + j];
+            for (int j = 0; j < kCluster; ++j) {
+                const float sx = a.s.x32[j0 + j], sy = a.s.y32[j0 + j], sz = a.s.z32[j0 + j];
+                const float gx = a.s.gx32[j0 + j], gy = a.s.gy32[j0 + j], gz = a.s.gz32[j0 + j];
 #pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        far_pair32(tx32[r], ty32[r], tz32[r], sx, sy, sz, gx, gy, gz, px[r], py[r], pz[r]);
-                }
+                for (int r = 0; r < R; ++r)
+                    far_pair32(tx32[r], ty32[r], tz32[r], sx, sy, sz, gx, gy, gz, px[r], py[r], pz[r]);
+            }
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    two_sum_acc(px[r], hx[r], lx[r]);
-                    two_sum_acc(py[r], hy[r], ly[r]);
-                    two_sum_acc(pz[r], hz[r], lz[r]);
-                }
-            } else {
-#pragma unroll 4
-                for (int j = 0; j < kCluster; ++j) {
-                    const double sx = a.s.x[j0 + j], sy = a.s.y[j0 + j], sz = a.s.z[j0 + j];
-                    const double gx = a.s.gx[j0 + j], gy = a.s.gy[j0 + j], gz = a.s.gz[j0 + j];
-#pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        far_pair64(tx[r], ty[r], tz[r], sx, sy, sz, gx, gy, gz, ax[r], ay[r], az[r]);
-                }
+            for (int r = 0; r < R; ++r) {
+                two_sum_acc(px[r], hx[r], lx[r]);
+                two_sum_acc(py[r], hy[r], ly[r]);
+                two_sum_acc(pz[r], hz[r], lz[r]);
             }
         } else {
-#pragma unroll 1
+#pragma unroll 4
             for (int j = 0; j < kCluster; ++j) {
                 const double sx = a.s.x[j0 + j], sy = a.s.y[j0 + j], sz = a.s.z[j0 + j];
                 const double gx = a.s.gx[j0 + j], gy = a.s.gy[j0 + j], gz = a.s.gz[j0 + j];
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    near_pair64(tx[r], ty[r], tz[r], sx, sy, sz, gx, gy, gz, VARD ? dcv[r] : dcu,
-                                ax[r], ay[r], az[r]);
+                    far_pair64(tx[r], ty[r], tz[r], sx, sy, sz, gx, gy, gz, ax[r], ay[r], az[r]);
             }
         }
     }
@@ -144,15 +152,71 @@ __global__ __launch_bounds__(kWave) void k_pair(PairArgs a)
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t i = t0 + r * kWave + lane;
-        double vx = ax[r], vy = ay[r], vz = az[r];
         if constexpr (MIXED) {
-            vx += (double)hx[r] + (double)lx[r];
-            vy += (double)hy[r] + (double)ly[r];
-            vz += (double)hz[r] + (double)lz[r];
+            px[i] = (double)hx[r] + (double)lx[r];
+            py[i] = (double)hy[r] + (double)ly[r];
+            pz[i] = (double)hz[r] + (double)lz[r];
+        } else {
+            px[i] = ax[r];
+            py[i] = ay[r];
+            pz[i] = az[r];
         }
-        px[i] = vx;
-        py[i] = vy;
-        pz[i] = vz;
+    }
+}
+
+template <int R, bool VARD>
+__global__ __launch_bounds__(kWave) void k_near(PairArgs a, const TBlockRec *__restrict__ tbr)
+{
+    const int split = (int)(blockIdx.x % (unsigned)a.n_splits);
+    const int tb = (int)(blockIdx.x / (unsigned)a.n_splits);
+    const int lane = threadIdx.x;
+    const int64_t t0 = (int64_t)tb * (kWave * R);
+    const int64_t np_t = a.t.np;
+    const TBlockRec rec = tbr[tb];
+
+    const int64_t n_cl = a.s.np / kCluster;
+    const int64_t c_begin = (int64_t)split * a.clusters_per_split;
+    const int64_t c_end = c_begin + a.clusters_per_split < n_cl ? c_begin + a.clusters_per_split : n_cl;
+    int64_t c = c_begin;
+    while (c < c_end && cluster_is_far(rec, a.s.sphere[c])) ++c;
+    if (c == c_end) return;                         // nothing near in this split
+
+    double tx[R], ty[R], tz[R], ax[R], ay[R], az[R];
+    DeltaC dcv[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = t0 + r * kWave + lane;
+        tx[r] = a.t.x[i];
+        ty[r] = a.t.y[i];
+        tz[r] = a.t.z[i];
+        if constexpr (VARD) dcv[r] = make_delta(a.t.delta[i]);
+        ax[r] = ay[r] = az[r] = 0.0;
+    }
+    const DeltaC dcu = make_delta(a.delta);
+
+    for (; c < c_end; ++c) {
+        if (cluster_is_far(rec, a.s.sphere[c])) continue;
+        const int64_t j0 = c * kCluster;
+#pragma unroll 1
+        for (int j = 0; j < kCluster; ++j) {
+            const double sx = a.s.x[j0 + j], sy = a.s.y[j0 + j], sz = a.s.z[j0 + j];
+            const double gx = a.s.gx[j0 + j], gy = a.s.gy[j0 + j], gz = a.s.gz[j0 + j];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                near_pair64(tx[r], ty[r], tz[r], sx, sy, sz, gx, gy, gz, VARD ? dcv[r] : dcu,
+                            ax[r], ay[r], az[r]);
+        }
+    }
+
+    double *px = a.part + ((int64_t)split * 3 + 0) * np_t;
+    double *py = a.part + ((int64_t)split * 3 + 1) * np_t;
+    double *pz = a.part + ((int64_t)split * 3 + 2) * np_t;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = t0 + r * kWave + lane;
+        px[i] += ax[r];
+        py[i] += ay[r];
+        pz[i] += az[r];
     }
 }
 
@@ -183,21 +247,30 @@ __global__ __launch_bounds__(256) void k_fill_zero(double *__restrict__ ux, doub
     if (i < n) { ux[i] = 0.0; uy[i] = 0.0; uz[i] = 0.0; }
 }
 
-template <int R, bool MIXED, bool VARD>
-hipError_t launch_t(const PairArgs &a, unsigned grid, hipStream_t st)
+template <int R>
+hipError_t launch_r(const PairArgs &a, const PairPlan &p, bool mixed, bool vard, hipStream_t st,
+                    const PairTiming *tm)
 {
-    hipLaunchKernelGGL((k_pair<R, MIXED, VARD>), dim3(grid), dim3(kWave), 0, st, a);
+    const unsigned grid = (unsigned)((int64_t)p.n_tblocks * p.n_splits);
+    TBlockRec *rec = reinterpret_cast<TBlockRec *>(a.tblock_scratch);
+    hipLaunchKernelGGL((k_tblock<R>), dim3(p.n_tblocks), dim3(kWave), 0, st, a, rec, (int)mixed);
+    if (tm && tm->e0) (void)hipEventRecord(tm->e0, st);
+    if (mixed)
+        hipLaunchKernelGGL((k_far<R, true>), dim3(grid), dim3(kWave), 0, st, a, rec);
+    else
+        hipLaunchKernelGGL((k_far<R, false>), dim3(grid), dim3(kWave), 0, st, a, rec);
+    if (tm && tm->e1) (void)hipEventRecord(tm->e1, st);
+    if (vard)
+        hipLaunchKernelGGL((k_near<R, true>), dim3(grid), dim3(kWave), 0, st, a, rec);
+    else
+        hipLaunchKernelGGL((k_near<R, false>), dim3(grid), dim3(kWave), 0, st, a, rec);
+    if (tm && tm->e2) (void)hipEventRecord(tm->e2, st);
     return hipGetLastError();
 }
 
-template <int R>
-hipError_t launch_r(const PairArgs &a, unsigned grid, bool mixed, bool vard, hipStream_t st)
-{
-    if (mixed) return vard ? launch_t<R, true, true>(a, grid, st) : launch_t<R, true, false>(a, grid, st);
-    return vard ? launch_t<R, false, true>(a, grid, st) : launch_t<R, false, false>(a, grid, st);
-}
-
 }  // namespace
+
+size_t tblock_scratch_bytes(int n_tblocks) { return (size_t)n_tblocks * sizeof(TBlockRec); }
 
 PairPlan plan_pairs(int64_t np_src, int64_t np_tgt, int R, int waves_wanted)
 {
@@ -214,13 +287,12 @@ PairPlan plan_pairs(int64_t np_src, int64_t np_tgt, int R, int waves_wanted)
 }
 
 hipError_t launch_pair(const PairArgs &a, const PairPlan &p, bool mixed, bool var_delta,
-                       hipStream_t st)
+                       hipStream_t st, const PairTiming *tm)
 {
-    const unsigned grid = (unsigned)((int64_t)p.n_tblocks * p.n_splits);
     switch (p.R) {
-    case 1: return launch_r<1>(a, grid, mixed, var_delta, st);
-    case 2: return launch_r<2>(a, grid, mixed, var_delta, st);
-    case 4: return launch_r<4>(a, grid, mixed, var_delta, st);
+    case 1: return launch_r<1>(a, p, mixed, var_delta, st, tm);
+    case 2: return launch_r<2>(a, p, mixed, var_delta, st, tm);
+    case 4: return launch_r<4>(a, p, mixed, var_delta, st, tm);
     default: return hipErrorInvalidValue;
     }
 }

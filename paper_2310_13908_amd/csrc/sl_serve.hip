@@ -10,7 +10,8 @@ extern "C" {
 void sl_destroy(sl_ctx *ctx)
 {
     if (!ctx) return;
-    for (auto &ev : ctx->timed) { (void)hipEventDestroy(ev.first); (void)hipEventDestroy(ev.second); }
+    for (auto &ev : ctx->timed)
+        for (hipEvent_t e : {ev.e0, ev.e1, ev.e2}) (void)hipEventDestroy(e);
     for (auto ev : ctx->spare_events) (void)hipEventDestroy(ev);
     delete ctx;
 }

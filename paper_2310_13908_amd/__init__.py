@@ -82,3 +82,48 @@ class Context:
                      U[0].data_ptr(), U[1].data_ptr(), U[2].data_ptr(), _stream_handle(stream))
         check(st, "sl_eval")
         return U.t()
+
+    # -- serving ---------------------------------------------------------------------------
+    def register_surface(self, X, w, delta) -> int:
+        """Copy nodes X (N, 3) and weights w (N,) into a resident surface; returns its handle."""
+        import torch
+        Xs = _soa(X)
+        ws = w.to(torch.float64).contiguous()
+        st, h = sl_surface_register(self.ptr, Xs.shape[1], Xs[0].data_ptr(), Xs[1].data_ptr(),
+                                    Xs[2].data_ptr(), ws.data_ptr(), float(delta))
+        check(st, "sl_surface_register")
+        return h
+
+    def release_surface(self, handle: int):
+        check(sl_surface_release(self.ptr, handle), "sl_surface_release")
+
+    def submit(self, handle: int, f, mu=1.0, precision="mixed", out=None):
+        """Queue u = S[f] on a resident surface; returns (request id, (3, N) output tensor).
+
+        The density copy and the output are kept alive here until the request is reported done.
+        """
+        import torch
+        fs = _soa(f)
+        U = out if out is not None else torch.empty_like(fs)
+        torch.cuda.current_stream().synchronize()    # fs / U are ready before the device reads them
+        st, rid = sl_submit(self.ptr, handle, PRECISIONS[precision], fs[0].data_ptr(),
+                            fs[1].data_ptr(), fs[2].data_ptr(), float(mu), U[0].data_ptr(),
+                            U[1].data_ptr(), U[2].data_ptr())
+        check(st, "sl_submit")
+        self._inflight = getattr(self, "_inflight", {})
+        self._inflight[rid] = (fs, U)
+        return rid, U
+
+    def wait(self, rid: int, timeout_s: float = 60.0):
+        check(sl_wait(self.ptr, rid, timeout_s), "sl_wait")
+        return self._inflight.pop(rid)[1].t()
+
+    def poll(self, rid: int) -> bool:
+        st, done = sl_poll(self.ptr, rid)
+        check(st, "sl_poll")
+        if done:
+            self._inflight.pop(rid, None)
+        return done
+
+    def stats(self):
+        return sl_get_stats(self.ptr)

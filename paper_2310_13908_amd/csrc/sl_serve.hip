@@ -1,32 +1,1004 @@
 // sl_serve.hip -- resident surfaces and the continuously batched persistent kernel.
+//
+// Design.
+//  * One HBM arena (the context's budget) holds every resident surface and the staging of every
+//    admitted request.  Admission = the request's staging fits in the arena (and a descriptor
+//    slot and ring space are free); requests that do not fit wait in FIFO order on the host and
+//    are admitted as memory is returned.  Nothing is hipMalloc'ed or hipFree'd while the
+//    persistent kernel runs (a free can synchronize the device).
+//  * Work items live in a ring of host-pinned, fine-grained memory: (slot, kind, a, b).
+//    kind GATHER packs g = w f for points [a, b) of the request into its staging (sorted order);
+//    kind PAIR sums every source of the surface for target block a (128 targets) and writes
+//    u = S[f] for those targets.  A request is published as its gather items followed by its
+//    pair items; pair items wait for the request's gathers (which were claimed earlier, so the
+//    wait is bounded).
+//  * One persistent kernel serves all requests: each wavefront claims the next item with a CAS
+//    on a device counter, runs it and counts it done; the wave finishing a request's last item
+//    publishes the request's sequence number to host memory with a system-scope release.
+//    Every wave exits once the ring is drained and either the host asked it to stop or no item
+//    was claimed for kIdleSeconds; the host relaunches it when new work arrives.  The only
+//    other wait (a pair item waiting for its request's gathers) is bounded as well.
+//  * Coherence: staging and surfaces are reused arena memory written while the kernel runs, so
+//    the kernel reads them only with vector loads after an acquire (never through the scalar
+//    cache, which is only invalidated at kernel launch); each lane loads one source of a
+//    cluster and the wave broadcasts it lane by lane with readlane.
+//  * Each target's sum runs in a fixed order (clusters ascending, one accumulator set) whatever
+//    else is in flight, so a request's result is bit-identical alone and in any mix.
+#include <math.h>
+#include <string.h>
+
+#include <chrono>
+#include <map>
+
 #include "sl_internal.h"
+
+namespace sl {
+
+namespace {
+
+constexpr int kServeR = 2;                       // targets per lane in a pair item
+constexpr int kServeBlock = kWave * kServeR;     // targets per pair item
+constexpr int64_t kGatherChunk = 4096;           // points per gather item
+constexpr int kMaxSlots = 1024;                  // admitted requests in flight
+constexpr uint64_t kRingCap = 1ull << 21;        // work items in the ring (power of two)
+constexpr int kServeWavesPerSimd = 4;
+constexpr double kIdleSeconds = 0.25;            // persistent kernel exits after this idle time
+constexpr double kGatherWaitSeconds = 2.0;       // bound on a pair item's wait for its gathers
+constexpr double kPollSeconds = 2e-6;            // spacing of the waves' host-memory polls
+
+enum : uint32_t { kItemGather = 0, kItemPair = 1 };
+
+struct WorkItem {
+    uint32_t slot, kind, a, b;
+};
+
+// Per-request descriptor in host-pinned memory (device reads it with uncached loads).
+struct ReqDesc {
+    const double *x, *y, *z, *w;          // surface, sorted
+    const float *x32, *y32, *z32;
+    const int32_t *perm;
+    const double4 *sphere;
+    const TBlockRec *tbr;
+    const double *fx, *fy, *fz;           // caller density (caller order)
+    double *ux, *uy, *uz;                 // caller output (caller order)
+    double *gx, *gy, *gz;                 // staging, sorted
+    float *gx32, *gy32, *gz32;
+    int64_t n, np;
+    double delta, scale;
+    uint64_t gather_target, items_target, seq;
+    int64_t mixed;
+};
+
+struct ServeCtl {                         // host-pinned
+    uint64_t tail;                        // items published (host writes)
+    uint64_t stop;                        // 1: drain and exit
+    uint64_t claimed;                     // device mirror of the claim counter (lower bound)
+    uint64_t error;                       // device sets 1 if a bounded wait gave up
+};
+
+struct DevCounters {                      // device memory
+    uint64_t head;                        // items claimed
+    uint64_t last_activity;               // wall clock of the latest claim
+    uint64_t tail_mirror;                 // latest host tail seen by any wave
+    uint64_t stop_mirror;                 // host stop flag seen by any wave
+    uint64_t last_poll;                   // wall clock of the latest read of host memory
+    uint64_t pad[3];
+    uint64_t gathers_done[kMaxSlots];     // monotonic per slot
+    uint64_t items_done[kMaxSlots];       // monotonic per slot
+};
+
+struct ServeArgs {
+    ServeCtl *ctl;
+    const WorkItem *ring;
+    const ReqDesc *desc;
+    uint64_t *done_seq;                   // host-pinned, per slot
+    DevCounters *dc;
+    uint64_t idle_ticks;                  // exit after this long without a claim
+    uint64_t wait_ticks;                  // longest wait of a pair item for its gathers
+    uint64_t poll_ticks;                  // spacing of the host-memory polls
+};
+
+// ------------------------------------------------------------------------------------------
+// Device helpers
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t ld_sys(const void *p)
+{
+    return __hip_atomic_load((uint64_t *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint64_t uni64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+// A descriptor field, read by every lane from host memory and made wave-uniform.
+template <typename T>
+__device__ __forceinline__ T field(const T *p)
+{
+    static_assert(sizeof(T) == 8, "64-bit fields only");
+    const uint64_t v = uni64(ld_sys(p));
+    T out;
+    memcpy(&out, &v, 8);
+    return out;
+}
+__device__ __forceinline__ float bcast(float v, int j)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+__device__ __forceinline__ double bcast(double v, int j)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, j);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), j);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ void idle_sleep(int rounds)
+{
+    for (int k = 0; k < rounds; ++k) __builtin_amdgcn_s_sleep(127);
+}
+
+__device__ void run_gather(const ServeArgs &a, const WorkItem &it)
+{
+    const ReqDesc *d = a.desc + it.slot;
+    const int32_t *perm = field(&d->perm);
+    const double *w = field(&d->w);
+    const double *fx = field(&d->fx), *fy = field(&d->fy), *fz = field(&d->fz);
+    double *gx = field(&d->gx), *gy = field(&d->gy), *gz = field(&d->gz);
+    float *gx32 = field(&d->gx32), *gy32 = field(&d->gy32), *gz32 = field(&d->gz32);
+    const int64_t mixed = field(&d->mixed);
+    for (int64_t p = (int64_t)it.a + threadIdx.x; p < (int64_t)it.b; p += kWave) {
+        const int32_t idx = perm[p];
+        double vx = 0.0, vy = 0.0, vz = 0.0;
+        if (idx >= 0) {
+            const double wt = w[p];
+            vx = wt * fx[idx]; vy = wt * fy[idx]; vz = wt * fz[idx];
+        }
+        gx[p] = vx; gy[p] = vy; gz[p] = vz;
+        if (mixed) { gx32[p] = (float)vx; gy32[p] = (float)vy; gz32[p] = (float)vz; }
+    }
+    __threadfence();
+    if (threadIdx.x == 0)
+        __hip_atomic_fetch_add(&a.dc->gathers_done[it.slot], 1ull, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ void run_pair(const ServeArgs &a, const WorkItem &it)
+{
+    constexpr int R = kServeR;
+    const int lane = threadIdx.x;
+    const ReqDesc *d = a.desc + it.slot;
+    // Wait until the request's density is packed.  Its gather items were claimed before this
+    // item by running waves, so the wait ends; it is still bounded, and on expiry the item
+    // reports an error to the host and completes without writing.
+    const uint64_t gather_target = field(&d->gather_target);
+    const uint64_t t_wait0 = wall_clock64();
+    bool ready = false;
+    for (int rounds = 1;; rounds = rounds < 8 ? rounds * 2 : 8) {
+        uint64_t g = 0;
+        if (lane == 0)
+            g = __hip_atomic_load(&a.dc->gathers_done[it.slot], __ATOMIC_ACQUIRE,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+        if (uni64(g) >= gather_target) {
+            ready = true;
+            break;
+        }
+        if (uni64(wall_clock64() - t_wait0 > a.wait_ticks ? 1u : 0u)) break;
+        idle_sleep(rounds);
+    }
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    if (!ready) {
+        if (lane == 0) {
+            __hip_atomic_store(&a.ctl->error, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            const uint64_t items_target = ld_sys(&d->items_target);
+            const uint64_t old = __hip_atomic_fetch_add(&a.dc->items_done[it.slot], 1ull,
+                                                        __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (old + 1 == items_target)
+                __hip_atomic_store(&a.done_seq[it.slot], ld_sys(&d->seq), __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        return;
+    }
+
+    const double *sx = field(&d->x), *sy = field(&d->y), *sz = field(&d->z);
+    const double *gx = field(&d->gx), *gy = field(&d->gy), *gz = field(&d->gz);
+    const float *sx32 = field(&d->x32), *sy32 = field(&d->y32), *sz32 = field(&d->z32);
+    const float *gx32 = field(&d->gx32), *gy32 = field(&d->gy32), *gz32 = field(&d->gz32);
+    const int32_t *perm = field(&d->perm);
+    const double4 *sphere = field(&d->sphere);
+    const TBlockRec *tbr = field(&d->tbr);
+    double *ux = field(&d->ux), *uy = field(&d->uy), *uz = field(&d->uz);
+    const int64_t np = field(&d->np);
+    const double delta = field(&d->delta), scale = field(&d->scale);
+    const int64_t mixed = field(&d->mixed);
+
+    const int64_t t0 = (int64_t)it.a * kServeBlock;
+    const TBlockRec rec = tbr[it.a];
+    const double gap_far = mixed ? rec.gap_far_mixed : rec.gap_far;
+    const DeltaC dc = make_delta(delta);
+    double tx[R], ty[R], tz[R], ax[R], ay[R], az[R];
+    float tx32[R], ty32[R], tz32[R], hx[R], hy[R], hz[R], lx[R], ly[R], lz[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = t0 + r * kWave + lane;
+        tx[r] = sx[i]; ty[r] = sy[i]; tz[r] = sz[i];
+        tx32[r] = mixed ? sx32[i] : 0.0f;
+        ty32[r] = mixed ? sy32[i] : 0.0f;
+        tz32[r] = mixed ? sz32[i] : 0.0f;
+        ax[r] = ay[r] = az[r] = 0.0;
+        hx[r] = hy[r] = hz[r] = lx[r] = ly[r] = lz[r] = 0.0f;
+    }
+
+    const int64_t n_cl = np / kCluster;
+    for (int64_t c = 0; c < n_cl; ++c) {
+        const int64_t j0 = c * kCluster;
+        const bool far = uni64(cluster_is_far(rec, sphere[c], gap_far) ? 1u : 0u) != 0;
+        if (far && mixed) {
+            const float vx = sx32[j0 + lane], vy = sy32[j0 + lane], vz = sz32[j0 + lane];
+            const float wx = gx32[j0 + lane], wy = gy32[j0 + lane], wz = gz32[j0 + lane];
+            float px[R], py[R], pz[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
+#pragma unroll 4
+            for (int j = 0; j < kCluster; ++j) {
+                const float s0 = bcast(vx, j), s1 = bcast(vy, j), s2 = bcast(vz, j);
+                const float g0 = bcast(wx, j), g1 = bcast(wy, j), g2 = bcast(wz, j);
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    far_pair32(tx32[r], ty32[r], tz32[r], s0, s1, s2, g0, g1, g2, px[r], py[r], pz[r]);
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                two_sum_acc(px[r], hx[r], lx[r]);
+                two_sum_acc(py[r], hy[r], ly[r]);
+                two_sum_acc(pz[r], hz[r], lz[r]);
+            }
+        } else {
+            const double vx = sx[j0 + lane], vy = sy[j0 + lane], vz = sz[j0 + lane];
+            const double wx = gx[j0 + lane], wy = gy[j0 + lane], wz = gz[j0 + lane];
+            if (far) {
+#pragma unroll 2
+                for (int j = 0; j < kCluster; ++j) {
+                    const double s0 = bcast(vx, j), s1 = bcast(vy, j), s2 = bcast(vz, j);
+                    const double g0 = bcast(wx, j), g1 = bcast(wy, j), g2 = bcast(wz, j);
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        far_pair64(tx[r], ty[r], tz[r], s0, s1, s2, g0, g1, g2, ax[r], ay[r], az[r]);
+                }
+            } else {
+#pragma unroll 1
+                for (int j = 0; j < kCluster; ++j) {
+                    const double s0 = bcast(vx, j), s1 = bcast(vy, j), s2 = bcast(vz, j);
+                    const double g0 = bcast(wx, j), g1 = bcast(wy, j), g2 = bcast(wz, j);
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        near_pair64(tx[r], ty[r], tz[r], s0, s1, s2, g0, g1, g2, dc, ax[r], ay[r], az[r]);
+                }
+            }
+        }
+    }
+
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = t0 + r * kWave + lane;
+        const int32_t idx = perm[i];
+        if (idx >= 0) {
+            ux[idx] = (ax[r] + ((double)hx[r] + (double)lx[r])) * scale;
+            uy[idx] = (ay[r] + ((double)hy[r] + (double)ly[r])) * scale;
+            uz[idx] = (az[r] + ((double)hz[r] + (double)lz[r])) * scale;
+        }
+    }
+    __threadfence();
+    if (lane == 0) {
+        const uint64_t items_target = ld_sys(&d->items_target);
+        const uint64_t old = __hip_atomic_fetch_add(&a.dc->items_done[it.slot], 1ull,
+                                                    __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1 == items_target) {
+            __threadfence_system();
+            __hip_atomic_store(&a.done_seq[it.slot], ld_sys(&d->seq), __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kWave) void k_serve(ServeArgs a)
+{
+    const int lane = threadIdx.x;
+    if (lane == 0)
+        __hip_atomic_fetch_max(&a.dc->last_activity, (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    int rounds = 0;
+    for (;;) {
+        uint64_t idx = 0, got = 0, quit = 0;
+        if (lane == 0) {
+            uint64_t h = __hip_atomic_load(&a.dc->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint64_t t = __hip_atomic_load(&a.dc->tail_mirror, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            if (h >= t) {
+                // At most one wave every ~2 us reads the host's tail and stop flag (PCIe) and
+                // mirrors them into device memory for the others.
+                const uint64_t now = wall_clock64();
+                uint64_t lp = __hip_atomic_load(&a.dc->last_poll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (now > lp + a.poll_ticks &&
+                    __hip_atomic_compare_exchange_strong(&a.dc->last_poll, &lp, now, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    t = __hip_atomic_load(&a.ctl->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                    const uint64_t stop = __hip_atomic_load(&a.ctl->stop, __ATOMIC_ACQUIRE,
+                                                            __HIP_MEMORY_SCOPE_SYSTEM);
+                    __hip_atomic_fetch_max(&a.dc->tail_mirror, t, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    if (stop)
+                        __hip_atomic_store(&a.dc->stop_mirror, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            if (h < t) {
+                if (__hip_atomic_compare_exchange_strong(&a.dc->head, &h, h + 1, __ATOMIC_ACQ_REL,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    got = 1;
+                    idx = h;
+                }
+            } else {
+                const uint64_t stop = __hip_atomic_load(&a.dc->stop_mirror, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t last = __hip_atomic_load(&a.dc->last_activity, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t now = wall_clock64();
+                if (stop || (now > last && now - last > a.idle_ticks)) quit = 1;
+            }
+        }
+        got = uni64(got);
+        if (!got) {
+            if (uni64(quit)) break;
+            rounds = rounds < 16 ? rounds + 1 : 16;
+            idle_sleep(rounds);
+            continue;
+        }
+        rounds = 0;
+        idx = uni64(idx);
+        if (lane == 0) {
+            __hip_atomic_fetch_max(&a.dc->last_activity, (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            // lower bound of the claim count for the host's ring-space check (plain store:
+            // out-of-order writers can only make it smaller, which is safe)
+            __hip_atomic_store(&a.ctl->claimed, idx + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        const WorkItem *slot = a.ring + (idx & (kRingCap - 1));
+        const uint64_t w0 = uni64(ld_sys(slot)), w1 = uni64(ld_sys((const uint64_t *)slot + 1));
+        WorkItem it;
+        it.slot = (uint32_t)w0;
+        it.kind = (uint32_t)(w0 >> 32);
+        it.a = (uint32_t)w1;
+        it.b = (uint32_t)(w1 >> 32);
+        __atomic_thread_fence(__ATOMIC_ACQUIRE);
+        if (it.kind == kItemGather)
+            run_gather(a, it);
+        else
+            run_pair(a, it);
+    }
+}
+
+// Surface packing at registration: sorted positions and weights, single-precision positions,
+// permutation, cluster spheres.
+__global__ __launch_bounds__(256) void k_gather_surface(
+    const uint32_t *__restrict__ order, int64_t n, const double *__restrict__ x,
+    const double *__restrict__ y, const double *__restrict__ z, const double *__restrict__ w,
+    const double *__restrict__ centre, double *ox, double *oy, double *oz, double *ow, float *ox32,
+    float *oy32, float *oz32, int32_t *operm, double4 *osphere)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool real = p < n;
+    const uint32_t idx = order[real ? p : n - 1];
+    const double px = x[idx], py = y[idx], pz = z[idx];
+    ox[p] = px; oy[p] = py; oz[p] = pz;
+    ow[p] = real ? w[idx] : 0.0;
+    ox32[p] = (float)(px - centre[0]);
+    oy32[p] = (float)(py - centre[1]);
+    oz32[p] = (float)(pz - centre[2]);
+    operm[p] = real ? (int32_t)idx : -1;
+    const double cx = 0.5 * (wave_min(px) + wave_max(px));
+    const double cy = 0.5 * (wave_min(py) + wave_max(py));
+    const double cz = 0.5 * (wave_min(pz) + wave_max(pz));
+    const double dx = px - cx, dy = py - cy, dz = pz - cz;
+    const double rad = sqrt(wave_max(fma(dx, dx, fma(dy, dy, __dmul_rn(dz, dz))))) * (1.0 + 0x1p-40);
+    if ((threadIdx.x % kWave) == 0) osphere[p / kCluster] = make_double4(cx, cy, cz, rad);
+}
+
+// Target-block records for pair items, with the far thresholds of both precisions.
+__global__ __launch_bounds__(kWave) void k_tblock_serve(const double *__restrict__ x,
+                                                        const double *__restrict__ y,
+                                                        const double *__restrict__ z,
+                                                        const double *__restrict__ bbox,
+                                                        double delta, double rho64,
+                                                        TBlockRec *__restrict__ out)
+{
+    const int tb = blockIdx.x, lane = threadIdx.x;
+    double px[kServeR], py[kServeR], pz[kServeR];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+    for (int r = 0; r < kServeR; ++r) {
+        const int64_t i = (int64_t)tb * kServeBlock + r * kWave + lane;
+        px[r] = x[i]; py[r] = y[i]; pz[r] = z[i];
+        lo[0] = fmin(lo[0], px[r]); hi[0] = fmax(hi[0], px[r]);
+        lo[1] = fmin(lo[1], py[r]); hi[1] = fmax(hi[1], py[r]);
+        lo[2] = fmin(lo[2], pz[r]); hi[2] = fmax(hi[2], pz[r]);
+    }
+    const double cx = 0.5 * (wave_min(lo[0]) + wave_max(hi[0]));
+    const double cy = 0.5 * (wave_min(lo[1]) + wave_max(hi[1]));
+    const double cz = 0.5 * (wave_min(lo[2]) + wave_max(hi[2]));
+    double rr = 0.0;
+#pragma unroll
+    for (int r = 0; r < kServeR; ++r) {
+        const double dx = px[r] - cx, dy = py[r] - cy, dz = pz[r] - cz;
+        rr = fmax(rr, fma(dx, dx, fma(dy, dy, __dmul_rn(dz, dz))));
+    }
+    rr = wave_max(rr);
+    if (lane == 0) {
+        const double bx = bbox[3] - bbox[0], by = bbox[4] - bbox[1], bz = bbox[5] - bbox[2];
+        TBlockRec rec;
+        rec.cx = cx; rec.cy = cy; rec.cz = cz;
+        rec.rad = sqrt(rr) * (1.0 + 0x1p-40);
+        rec.gap_far = kRhoExact64 * delta;
+        rec.gap_far_mixed = fmax(rho64 * delta, 0x1p-10 * sqrt(fma(bx, bx, fma(by, by, __dmul_rn(bz, bz)))));
+        rec.pad0 = rec.pad1 = 0.0;
+        out[tb] = rec;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Host side
+// ------------------------------------------------------------------------------------------
+// First-fit allocator over one device buffer (offsets aligned to 256 bytes).
+class Arena {
+public:
+    char *base = nullptr;
+    size_t size = 0, used = 0;
+
+    void init(char *b, size_t s)
+    {
+        base = b;
+        size = s;
+        free_[0] = s;
+    }
+    char *alloc(size_t bytes)
+    {
+        bytes = (size_t)round_up((int64_t)bytes, 256);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const size_t off = it->first, len = it->second;
+                free_.erase(it);
+                if (len > bytes) free_[off + bytes] = len - bytes;
+                used += bytes;
+                sizes_[off] = bytes;
+                return base + off;
+            }
+        }
+        return nullptr;
+    }
+    void release(char *p)
+    {
+        const size_t off = (size_t)(p - base);
+        auto s = sizes_.find(off);
+        if (s == sizes_.end()) return;
+        size_t len = s->second;
+        sizes_.erase(s);
+        used -= len;
+        size_t start = off;
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && next->first == off + len) {
+            len += next->second;
+            free_.erase(next);
+        }
+        auto prev = free_.lower_bound(off);
+        if (prev != free_.begin()) {
+            --prev;
+            if (prev->first + prev->second == off) {
+                start = prev->first;
+                len += prev->second;
+                free_.erase(prev);
+            }
+        }
+        free_[start] = len;
+    }
+
+private:
+    std::map<size_t, size_t> free_;    // offset -> length
+    std::map<size_t, size_t> sizes_;   // offset -> length of live blocks
+};
+
+struct Surface {
+    int64_t n = 0, np = 0;
+    double delta = 0.0;
+    char *mem = nullptr;
+    double *x, *y, *z, *w;
+    float *x32, *y32, *z32;
+    int32_t *perm;
+    double4 *sphere;
+    TBlockRec *tbr;
+    int refs = 0;
+    bool released = false;
+};
+
+enum class ReqState { Pending, Active, Done, Failed };
+
+struct HostReq {
+    uint64_t id = 0;
+    uint64_t surf = 0;
+    bool mixed = false;
+    const double *fx, *fy, *fz;
+    double *ux, *uy, *uz;
+    double mu = 1.0;
+    ReqState state = ReqState::Pending;
+    int slot = -1;
+    char *staging = nullptr;
+    uint64_t seq = 0;
+    uint64_t n_items = 0;
+};
+
+}  // namespace
+
+struct Server {
+    sl_ctx *ctx = nullptr;
+    std::mutex mu;
+    std::condition_variable cv;          // progress thread wake-up
+    std::condition_variable done_cv;     // waiters
+    std::thread thread;
+    bool quit = false;
+    sl_status fatal = SL_OK;
+    std::string fatal_msg;
+
+    Arena arena;
+    char *arena_mem = nullptr;
+    hipStream_t kstream = nullptr, aux = nullptr;
+    hipEvent_t kdone = nullptr;
+    double clock_hz = 100e6;             // rate of the device's constant wall clock
+    bool kernel_launched = false;
+
+    ServeCtl *ctl = nullptr;
+    WorkItem *ring = nullptr;
+    ReqDesc *desc = nullptr;
+    uint64_t *done_seq = nullptr;
+    DevCounters *dc = nullptr;
+    uint64_t gathers_cum[kMaxSlots] = {};
+    uint64_t items_cum[kMaxSlots] = {};
+    std::vector<int> free_slots;
+
+    std::unordered_map<uint64_t, Surface> surfaces;
+    std::unordered_map<uint64_t, HostReq> reqs;
+    std::deque<uint64_t> pending;
+    std::vector<uint64_t> active;
+    uint64_t next_surface = 1, next_req = 1, next_seq = 1;
+    uint64_t tail = 0;
+    sl_stats stats = {};
+
+    sl_status init(sl_ctx *c);
+    void shutdown();
+    void loop();
+    void complete_locked();
+    void admit_locked();
+    sl_status ensure_kernel_locked();
+    void free_surface_locked(uint64_t h);
+};
+
+namespace {
+
+size_t surface_bytes(int64_t np)
+{
+    const int64_t nb = np / kServeBlock;
+    return (size_t)(4 * round_up(np * 8, 256) + 3 * round_up(np * 4, 256) + round_up(np * 4, 256) +
+                    round_up(np / kCluster * (int64_t)sizeof(double4), 256) +
+                    round_up(nb * (int64_t)sizeof(TBlockRec), 256));
+}
+
+size_t staging_bytes(int64_t np, bool mixed)
+{
+    return (size_t)(3 * round_up(np * 8, 256) + (mixed ? 3 * round_up(np * 4, 256) : 0));
+}
+
+}  // namespace
+
+sl_status Server::init(sl_ctx *c)
+{
+    ctx = c;
+    SL_HIP(hipStreamCreateWithFlags(&kstream, hipStreamNonBlocking));
+    SL_HIP(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
+    SL_HIP(hipEventCreateWithFlags(&kdone, hipEventDisableTiming));
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device) == hipSuccess && khz > 0)
+        clock_hz = 1e3 * (double)khz;
+    SL_HIP(hipHostMalloc((void **)&ctl, sizeof(ServeCtl), hipHostMallocCoherent | hipHostMallocMapped));
+    SL_HIP(hipHostMalloc((void **)&ring, sizeof(WorkItem) * kRingCap, hipHostMallocCoherent | hipHostMallocMapped));
+    SL_HIP(hipHostMalloc((void **)&desc, sizeof(ReqDesc) * kMaxSlots, hipHostMallocCoherent | hipHostMallocMapped));
+    SL_HIP(hipHostMalloc((void **)&done_seq, sizeof(uint64_t) * kMaxSlots, hipHostMallocCoherent | hipHostMallocMapped));
+    memset((void *)ctl, 0, sizeof(ServeCtl));
+    memset((void *)desc, 0, sizeof(ReqDesc) * kMaxSlots);
+    memset((void *)done_seq, 0, sizeof(uint64_t) * kMaxSlots);
+    SL_HIP(hipMalloc((void **)&dc, sizeof(DevCounters)));
+    SL_HIP(hipMemsetAsync(dc, 0, sizeof(DevCounters), aux));
+    size_t bytes = ctx->budget;
+    SL_HIP(hipMalloc((void **)&arena_mem, bytes));
+    SL_HIP(hipStreamSynchronize(aux));
+    arena.init(arena_mem, bytes);
+    for (int s = kMaxSlots - 1; s >= 0; --s) free_slots.push_back(s);
+    thread = std::thread([this] { loop(); });
+    return SL_OK;
+}
+
+void Server::shutdown()
+{
+    {
+        std::unique_lock<std::mutex> l(mu);
+        quit = true;
+    }
+    cv.notify_all();
+    if (thread.joinable()) thread.join();
+    // Drain: the kernel processes every published item, then sees `stop` and exits.
+    __atomic_store_n(&ctl->stop, 1ull, __ATOMIC_RELEASE);
+    if (kstream) (void)hipStreamSynchronize(kstream);
+    if (aux) (void)hipStreamSynchronize(aux);
+    if (arena_mem) (void)hipFree(arena_mem);
+    if (dc) (void)hipFree(dc);
+    if (ctl) (void)hipHostFree(ctl);
+    if (ring) (void)hipHostFree(ring);
+    if (desc) (void)hipHostFree(desc);
+    if (done_seq) (void)hipHostFree(done_seq);
+    if (kdone) (void)hipEventDestroy(kdone);
+    if (kstream) (void)hipStreamDestroy(kstream);
+    if (aux) (void)hipStreamDestroy(aux);
+}
+
+void Server::free_surface_locked(uint64_t h)
+{
+    auto it = surfaces.find(h);
+    if (it == surfaces.end()) return;
+    arena.release(it->second.mem);
+    surfaces.erase(it);
+}
+
+void Server::complete_locked()
+{
+    bool any = false;
+    for (size_t k = 0; k < active.size();) {
+        HostReq &r = reqs[active[k]];
+        const uint64_t seen = __atomic_load_n(&done_seq[r.slot], __ATOMIC_ACQUIRE);
+        if (seen != r.seq) {
+            ++k;
+            continue;
+        }
+        r.state = ReqState::Done;
+        arena.release(r.staging);
+        r.staging = nullptr;
+        free_slots.push_back(r.slot);
+        Surface &s = surfaces[r.surf];
+        if (--s.refs == 0 && s.released) free_surface_locked(r.surf);
+        stats.requests_done += 1;
+        stats.items_done += r.n_items;
+        active[k] = active.back();
+        active.pop_back();
+        any = true;
+    }
+    if (any) done_cv.notify_all();
+}
+
+void Server::admit_locked()
+{
+    while (!pending.empty()) {
+        HostReq &r = reqs[pending.front()];
+        Surface &s = surfaces[r.surf];
+        const uint64_t n_gather = (uint64_t)((s.np + kGatherChunk - 1) / kGatherChunk);
+        const uint64_t n_pair = (uint64_t)(s.np / kServeBlock);
+        const uint64_t claimed = __atomic_load_n(&ctl->claimed, __ATOMIC_ACQUIRE);
+        if (free_slots.empty() || tail + n_gather + n_pair - claimed > kRingCap) break;
+        char *st = arena.alloc(staging_bytes(s.np, r.mixed));
+        if (!st) break;
+        const int slot = free_slots.back();
+        free_slots.pop_back();
+        r.slot = slot;
+        r.staging = st;
+        r.seq = next_seq++;
+        r.n_items = n_gather + n_pair;
+        r.state = ReqState::Active;
+        ReqDesc d;
+        d.x = s.x; d.y = s.y; d.z = s.z; d.w = s.w;
+        d.x32 = s.x32; d.y32 = s.y32; d.z32 = s.z32;
+        d.perm = s.perm; d.sphere = s.sphere; d.tbr = s.tbr;
+        d.fx = r.fx; d.fy = r.fy; d.fz = r.fz;
+        d.ux = r.ux; d.uy = r.uy; d.uz = r.uz;
+        char *p = st;
+        d.gx = (double *)p; p += round_up(s.np * 8, 256);
+        d.gy = (double *)p; p += round_up(s.np * 8, 256);
+        d.gz = (double *)p; p += round_up(s.np * 8, 256);
+        if (r.mixed) {
+            d.gx32 = (float *)p; p += round_up(s.np * 4, 256);
+            d.gy32 = (float *)p; p += round_up(s.np * 4, 256);
+            d.gz32 = (float *)p;
+        } else {
+            d.gx32 = d.gy32 = d.gz32 = nullptr;
+        }
+        d.n = s.n;
+        d.np = s.np;
+        d.delta = s.delta;
+        d.scale = 1.0 / (8.0 * M_PI * r.mu);
+        gathers_cum[slot] += n_gather;
+        items_cum[slot] += n_pair;
+        d.gather_target = gathers_cum[slot];
+        d.items_target = items_cum[slot];
+        d.seq = r.seq;
+        d.mixed = r.mixed ? 1 : 0;
+        memcpy((void *)&desc[slot], &d, sizeof(d));
+        for (uint64_t k = 0; k < n_gather; ++k) {
+            const int64_t a = (int64_t)k * kGatherChunk;
+            const int64_t b = a + kGatherChunk < s.np ? a + kGatherChunk : s.np;
+            ring[(tail + k) & (kRingCap - 1)] = WorkItem{(uint32_t)slot, kItemGather, (uint32_t)a, (uint32_t)b};
+        }
+        for (uint64_t k = 0; k < n_pair; ++k)
+            ring[(tail + n_gather + k) & (kRingCap - 1)] = WorkItem{(uint32_t)slot, kItemPair, (uint32_t)k, 0u};
+        tail += n_gather + n_pair;
+        __atomic_store_n(&ctl->tail, tail, __ATOMIC_RELEASE);
+        active.push_back(r.id);
+        pending.pop_front();
+    }
+}
+
+sl_status Server::ensure_kernel_locked()
+{
+    // (Re)launch only when published items may be unclaimed and no kernel is running.  The
+    // claim mirror is a lower bound, so at worst this starts a kernel that idles out.
+    const uint64_t claimed = __atomic_load_n(&ctl->claimed, __ATOMIC_ACQUIRE);
+    if (claimed >= tail) return SL_OK;
+    if (kernel_launched) {
+        const hipError_t q = hipEventQuery(kdone);
+        if (q == hipErrorNotReady) return SL_OK;          // still running
+        if (q != hipSuccess) return hip_fail(q, "serving kernel");
+    }
+    ServeArgs a{ctl, ring, desc, done_seq, dc,
+                (uint64_t)(kIdleSeconds * clock_hz), (uint64_t)(kGatherWaitSeconds * clock_hz),
+                (uint64_t)(kPollSeconds * clock_hz) + 1};
+    const unsigned grid = (unsigned)(ctx->n_cu * 4 * kServeWavesPerSimd);
+    hipLaunchKernelGGL(k_serve, dim3(grid), dim3(kWave), 0, kstream, a);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(kdone, kstream);
+    if (e != hipSuccess) return hip_fail(e, "serving kernel launch");
+    kernel_launched = true;
+    stats.kernel_launches += 1;
+    return SL_OK;
+}
+
+void Server::loop()
+{
+    (void)hipSetDevice(ctx->device);
+    std::unique_lock<std::mutex> l(mu);
+    while (!quit) {
+        complete_locked();
+        admit_locked();
+        if (fatal == SL_OK && __atomic_load_n(&ctl->error, __ATOMIC_ACQUIRE)) {
+            fatal = SL_EHIP;
+            fatal_msg = "serving kernel: a work item gave up waiting for its request's density";
+            done_cv.notify_all();
+        }
+        if (fatal == SL_OK) {
+            const sl_status st = ensure_kernel_locked();
+            if (st != SL_OK) {
+                fatal = st;
+                fatal_msg = sl_last_error();
+                done_cv.notify_all();
+            }
+        }
+        if (active.empty() && pending.empty())
+            cv.wait(l);
+        else
+            cv.wait_for(l, std::chrono::microseconds(20));
+    }
+}
+
+void server_stats(sl_ctx *ctx, sl_stats *out)
+{
+    Server *s = ctx->server;
+    if (!s) return;
+    std::lock_guard<std::mutex> l(s->mu);
+    out->requests_done = s->stats.requests_done;
+    out->items_done = s->stats.items_done;
+    out->kernel_launches = s->stats.kernel_launches;
+    out->bytes_admitted = s->arena.used;
+}
+
+}  // namespace sl
 
 using namespace sl;
 
-void sl::server_stats(sl_ctx *, sl_stats *) {}
+namespace {
+
+sl_status get_server(sl_ctx *ctx, Server **out)
+{
+    std::lock_guard<std::mutex> l(ctx->mu);
+    if (!ctx->server) {
+        Server *s = new Server();
+        hipSetDevice(ctx->device);
+        const sl_status st = s->init(ctx);
+        if (st != SL_OK) {
+            s->shutdown();
+            delete s;
+            return st;
+        }
+        ctx->server = s;
+    }
+    *out = ctx->server;
+    return SL_OK;
+}
+
+bool ranges_overlap(const void *a, const void *b, int64_t bytes)
+{
+    const char *x = (const char *)a, *y = (const char *)b;
+    return a && b && x < y + bytes && y < x + bytes;
+}
+
+}  // namespace
 
 extern "C" {
 
 void sl_destroy(sl_ctx *ctx)
 {
     if (!ctx) return;
+    if (ctx->server) {
+        (void)hipSetDevice(ctx->device);
+        ctx->server->shutdown();
+        delete ctx->server;
+        ctx->server = nullptr;
+    }
     for (auto &ev : ctx->timed)
         for (hipEvent_t e : {ev.e0, ev.e1, ev.e2}) (void)hipEventDestroy(e);
     for (auto ev : ctx->spare_events) (void)hipEventDestroy(ev);
     delete ctx;
 }
 
-sl_status sl_surface_register(sl_ctx *, int64_t, const double *, const double *, const double *,
-                              const double *, double, uint64_t *)
+sl_status sl_surface_register(sl_ctx *ctx, int64_t n, const double *x, const double *y,
+                              const double *z, const double *w, double delta, uint64_t *handle)
 {
-    return fail(SL_EINVAL, "serving not built");
+    if (!ctx || !handle) return fail(SL_EINVAL, "sl_surface_register: NULL argument");
+    if (n < 1 || n > ((int64_t)1 << 30)) return fail(SL_EINVAL, "sl_surface_register: n must be in 1..2^30");
+    if (!x || !y || !z || !w) return fail(SL_EINVAL, "sl_surface_register: NULL array");
+    if (!isfinite(delta) || !(delta > 0.0)) return fail(SL_EINVAL, "sl_surface_register: bad delta");
+    Server *s = nullptr;
+    sl_status st = get_server(ctx, &s);
+    if (st != SL_OK) return st;
+    (void)hipSetDevice(ctx->device);
+    const int64_t np = round_up(n, kPad);
+    Surface sf;
+    sf.n = n;
+    sf.np = np;
+    sf.delta = delta;
+    {
+        std::lock_guard<std::mutex> l(s->mu);
+        sf.mem = s->arena.alloc(surface_bytes(np));
+        if (!sf.mem)
+            return fail(SL_EBUSY, "sl_surface_register: surface does not fit the HBM budget");
+    }
+    char *p = sf.mem;
+    auto take = [&](int64_t bytes) { char *q = p; p += round_up(bytes, 256); return q; };
+    sf.x = (double *)take(np * 8); sf.y = (double *)take(np * 8); sf.z = (double *)take(np * 8);
+    sf.w = (double *)take(np * 8);
+    sf.x32 = (float *)take(np * 4); sf.y32 = (float *)take(np * 4); sf.z32 = (float *)take(np * 4);
+    sf.perm = (int32_t *)take(np * 4);
+    sf.sphere = (double4 *)take(np / kCluster * (int64_t)sizeof(double4));
+    sf.tbr = (TBlockRec *)take(np / kServeBlock * (int64_t)sizeof(TBlockRec));
+
+    PackScratch ps;
+    char *scratch = nullptr;
+    hipError_t e = hipMallocAsync((void **)&scratch, sort_scratch_bytes(n), s->aux);
+    if (e == hipSuccess) {
+        carve_sort_scratch(scratch, n, ps);
+        e = launch_bbox(x, y, z, n, nullptr, nullptr, nullptr, 0, ps, s->aux);
+    }
+    const uint32_t *order = nullptr;
+    if (e == hipSuccess) e = launch_sort_points(x, y, z, n, ps, &order, s->aux);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_gather_surface, dim3((unsigned)(np / 256)), dim3(256), 0, s->aux, order,
+                           n, x, y, z, w, ps.centre, sf.x, sf.y, sf.z, sf.w, sf.x32, sf.y32, sf.z32,
+                           sf.perm, sf.sphere);
+        hipLaunchKernelGGL(k_tblock_serve, dim3((unsigned)(np / kServeBlock)), dim3(kWave), 0, s->aux,
+                           sf.x, sf.y, sf.z, ps.bbox, delta, ctx->rho64, sf.tbr);
+        e = hipGetLastError();
+    }
+    if (scratch) (void)hipFreeAsync(scratch, s->aux);
+    const hipError_t es = hipStreamSynchronize(s->aux);
+    if (e == hipSuccess) e = es;
+    std::lock_guard<std::mutex> l(s->mu);
+    if (e != hipSuccess) {
+        s->arena.release(sf.mem);
+        return hip_fail(e, "sl_surface_register");
+    }
+    const uint64_t h = s->next_surface++;
+    s->surfaces[h] = sf;
+    *handle = h;
+    return SL_OK;
 }
-sl_status sl_surface_release(sl_ctx *, uint64_t) { return fail(SL_EINVAL, "serving not built"); }
-sl_status sl_submit(sl_ctx *, uint64_t, sl_precision, const double *, const double *,
-                    const double *, double, double *, double *, double *, uint64_t *)
+
+sl_status sl_surface_release(sl_ctx *ctx, uint64_t handle)
 {
-    return fail(SL_EINVAL, "serving not built");
+    if (!ctx) return fail(SL_EINVAL, "sl_surface_release: ctx is NULL");
+    Server *s = ctx->server;
+    if (!s) return fail(SL_ENOTFOUND, "sl_surface_release: unknown handle");
+    std::lock_guard<std::mutex> l(s->mu);
+    auto it = s->surfaces.find(handle);
+    if (it == s->surfaces.end() || it->second.released)
+        return fail(SL_ENOTFOUND, "sl_surface_release: unknown handle");
+    it->second.released = true;
+    if (it->second.refs == 0) s->free_surface_locked(handle);
+    return SL_OK;
 }
-sl_status sl_poll(sl_ctx *, uint64_t, int *) { return fail(SL_EINVAL, "serving not built"); }
-sl_status sl_wait(sl_ctx *, uint64_t, double) { return fail(SL_EINVAL, "serving not built"); }
+
+sl_status sl_submit(sl_ctx *ctx, uint64_t handle, sl_precision prec, const double *fx,
+                    const double *fy, const double *fz, double mu, double *ux, double *uy,
+                    double *uz, uint64_t *request)
+{
+    if (!ctx || !request) return fail(SL_EINVAL, "sl_submit: NULL argument");
+    if (prec != SL_FP64 && prec != SL_MIXED) return fail(SL_EINVAL, "sl_submit: unknown precision");
+    if (!isfinite(mu) || !(mu > 0.0)) return fail(SL_EINVAL, "sl_submit: mu must be finite and > 0");
+    if (!fx || !fy || !fz || !ux || !uy || !uz) return fail(SL_EINVAL, "sl_submit: NULL array");
+    Server *s = ctx->server;
+    if (!s) return fail(SL_ENOTFOUND, "sl_submit: unknown surface");
+    std::lock_guard<std::mutex> l(s->mu);
+    if (s->fatal != SL_OK) return fail(s->fatal, s->fatal_msg);
+    auto it = s->surfaces.find(handle);
+    if (it == s->surfaces.end() || it->second.released) return fail(SL_ENOTFOUND, "sl_submit: unknown surface");
+    Surface &sf = it->second;
+    const int64_t bytes = sf.n * 8;
+    const double *ins[3] = {fx, fy, fz};
+    double *outs[3] = {ux, uy, uz};
+    for (int a = 0; a < 3; ++a) {
+        for (int b = 0; b < 3; ++b)
+            if (ranges_overlap(outs[a], ins[b], bytes)) return fail(SL_EINVAL, "sl_submit: output aliases input");
+        for (int b = a + 1; b < 3; ++b)
+            if (ranges_overlap(outs[a], outs[b], bytes)) return fail(SL_EINVAL, "sl_submit: outputs overlap");
+    }
+    if (staging_bytes(sf.np, prec == SL_MIXED) > s->arena.size)
+        return fail(SL_EBUSY, "sl_submit: request staging exceeds the whole HBM budget");
+    if ((uint64_t)((sf.np + kGatherChunk - 1) / kGatherChunk + sf.np / kServeBlock) > kRingCap)
+        return fail(SL_EINVAL, "sl_submit: surface needs more work items than the queue holds");
+    HostReq r;
+    r.id = s->next_req++;
+    r.surf = handle;
+    r.mixed = prec == SL_MIXED;
+    r.fx = fx; r.fy = fy; r.fz = fz;
+    r.ux = ux; r.uy = uy; r.uz = uz;
+    r.mu = mu;
+    sf.refs += 1;
+    s->reqs[r.id] = r;
+    s->pending.push_back(r.id);
+    *request = r.id;
+    s->cv.notify_all();
+    return SL_OK;
 }
+
+sl_status sl_poll(sl_ctx *ctx, uint64_t request, int *done)
+{
+    if (!ctx || !done) return fail(SL_EINVAL, "sl_poll: NULL argument");
+    Server *s = ctx->server;
+    if (!s) return fail(SL_ENOTFOUND, "sl_poll: unknown request");
+    std::lock_guard<std::mutex> l(s->mu);
+    auto it = s->reqs.find(request);
+    if (it == s->reqs.end()) return fail(SL_ENOTFOUND, "sl_poll: unknown request");
+    if (s->fatal != SL_OK) return fail(s->fatal, s->fatal_msg);
+    *done = it->second.state == ReqState::Done;
+    if (*done) s->reqs.erase(it);
+    return SL_OK;
+}
+
+sl_status sl_wait(sl_ctx *ctx, uint64_t request, double timeout_s)
+{
+    if (!ctx) return fail(SL_EINVAL, "sl_wait: ctx is NULL");
+    if (!(timeout_s >= 0.0)) return fail(SL_EINVAL, "sl_wait: negative timeout");
+    Server *s = ctx->server;
+    if (!s) return fail(SL_ENOTFOUND, "sl_wait: unknown request");
+    std::unique_lock<std::mutex> l(s->mu);
+    auto it = s->reqs.find(request);
+    if (it == s->reqs.end()) return fail(SL_ENOTFOUND, "sl_wait: unknown request");
+    const auto deadline = std::chrono::steady_clock::now() +
+                          std::chrono::microseconds((int64_t)(timeout_s * 1e6));
+    while (s->reqs[request].state != ReqState::Done && s->fatal == SL_OK) {
+        if (s->done_cv.wait_until(l, deadline) == std::cv_status::timeout &&
+            s->reqs[request].state != ReqState::Done)
+            return fail(SL_ETIMEDOUT, "sl_wait: timed out");
+    }
+    if (s->fatal != SL_OK) return fail(s->fatal, s->fatal_msg);
+    s->reqs.erase(request);
+    return SL_OK;
+}
+
+}  // extern "C"

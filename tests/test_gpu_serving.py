@@ -1,0 +1,151 @@
+"""Serving: resident surfaces, HBM-footprint admission and the continuously batched persistent
+kernel.  Parity with the oracle, bit-identical results alone vs in a mix, admission under a
+small budget, release/lookup errors and relaunch of the kernel after it idles out."""
+import math
+import time
+
+import numpy as np
+import pytest
+
+from capsule_inputs import ELLIPSOID_SERVING, RBC, SPHERE, make_surface, sh_force
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "mixed": 1e-6}
+
+
+def eps(u, ref):
+    return float(np.max(np.abs(u - ref)) / np.max(np.abs(ref)))
+
+
+def dev_t(a):
+    import torch
+    return torch.as_tensor(np.asarray(a, dtype=np.float64), device=torch.device("cuda", 0))
+
+
+@pytest.fixture(scope="module")
+def surfaces():
+    out = []
+    for k, (shape, n) in enumerate([(SPHERE, 10), (ELLIPSOID_SERVING, 17), (RBC, 28), (RBC, 6)]):
+        s = make_surface(shape, n)
+        out.append((s, sh_force(s.x0, 500 + k), 2 * math.pi / (n + 1)))
+    return out
+
+
+@pytest.fixture(scope="module")
+def refs(surfaces):
+    import oracle
+    return [oracle.single_layer(s.X, s.w, f, d, mu=0.8) for s, f, d in surfaces]
+
+
+@pytest.fixture()
+def ctx():
+    import paper_2310_13908_amd as P
+    c = P.Context(0, hbm_budget_bytes=256 << 20)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_requests_match_oracle(ctx, surfaces, refs, precision):
+    hs = [ctx.register_surface(dev_t(s.X), dev_t(s.w), d) for s, f, d in surfaces]
+    rids = [ctx.submit(h, dev_t(f), mu=0.8, precision=precision)[0]
+            for h, (s, f, d) in zip(hs, surfaces)]
+    for rid, ref in zip(rids, refs):
+        u = ctx.wait(rid, 60.0).cpu().numpy()
+        assert eps(u, ref) < TOL[precision]
+    st = ctx.stats()
+    assert st.requests_done == len(rids) and st.kernel_launches >= 1
+
+
+def test_alone_equals_mixed_bitwise(ctx, surfaces):
+    """The same request served alone and inside a burst of other requests gives identical bits."""
+    s, f, d = surfaces[2]
+    h = ctx.register_surface(dev_t(s.X), dev_t(s.w), d)
+    others = [ctx.register_surface(dev_t(o.X), dev_t(o.w), od) for o, of, od in surfaces]
+    for precision in ("fp64", "mixed"):
+        rid, _ = ctx.submit(h, dev_t(f), mu=0.8, precision=precision)
+        alone = ctx.wait(rid).cpu().numpy()
+        burst = []
+        for k in range(12):
+            o, of, od = surfaces[k % len(surfaces)]
+            burst.append(ctx.submit(others[k % len(surfaces)], dev_t(of * (1 + k)), mu=0.8,
+                                    precision=("fp64", "mixed")[k % 2])[0])
+            if k == 5:
+                mid, _ = ctx.submit(h, dev_t(f), mu=0.8, precision=precision)
+        mixed = ctx.wait(mid).cpu().numpy()
+        for r in burst:
+            ctx.wait(r)
+        assert np.array_equal(alone, mixed)
+
+
+def test_admission_under_small_budget(surfaces, refs):
+    """Budget that holds the surfaces but only a couple of requests' staging at a time:
+    every request still completes, correctly, and the admitted bytes stay within the budget."""
+    import paper_2310_13908_amd as P
+    s, f, d = surfaces[2]
+    np_pad = ((s.N + 255) // 256) * 256
+    surf_bytes = np_pad * (4 * 8 + 3 * 4 + 4) + np_pad // 64 * 32 + np_pad // 128 * 64 + 8 * 256
+    stage = np_pad * (3 * 8 + 3 * 4) + 6 * 256
+    budget = surf_bytes + stage + stage // 5          # one request's staging at a time
+    with P.Context(0, hbm_budget_bytes=budget) as c:
+        h = c.register_surface(dev_t(s.X), dev_t(s.w), d)
+        with pytest.raises(P.SlError) as ei:           # a second copy does not fit
+            c.register_surface(dev_t(s.X), dev_t(s.w), d)
+        assert ei.value.status == P.SL_EBUSY
+        rids = [c.submit(h, dev_t(f * (k + 1)), mu=0.8, precision="mixed")[0] for k in range(8)]
+        for k, rid in enumerate(rids):
+            u = c.wait(rid, 120.0).cpu().numpy()
+            assert eps(u, refs[2] * (k + 1)) < TOL["mixed"]
+        st = c.stats()
+        assert st.requests_done == 8
+        assert st.bytes_admitted <= budget
+
+
+def test_release_and_errors(ctx, surfaces, refs):
+    import paper_2310_13908_amd as P
+    s, f, d = surfaces[3]
+    h = ctx.register_surface(dev_t(s.X), dev_t(s.w), d)
+    rid, _ = ctx.submit(h, dev_t(f), mu=0.8, precision="fp64")
+    ctx.release_surface(h)                       # in flight: memory returned after completion
+    u = ctx.wait(rid).cpu().numpy()
+    assert eps(u, refs[3]) < TOL["fp64"]
+    with pytest.raises(P.SlError) as ei:
+        ctx.submit(h, dev_t(f), mu=0.8)
+    assert ei.value.status == P.SL_ENOTFOUND
+    with pytest.raises(P.SlError) as ei:
+        ctx.release_surface(h)
+    assert ei.value.status == P.SL_ENOTFOUND
+    assert P.sl_wait(ctx.ptr, rid, 1.0) == P.SL_ENOTFOUND          # already retired
+    assert P.sl_poll(ctx.ptr, 987654321)[0] == P.SL_ENOTFOUND
+    h2 = ctx.register_surface(dev_t(s.X), dev_t(s.w), d)
+    with pytest.raises(P.SlError) as ei:
+        ctx.submit(h2, dev_t(f), mu=-1.0)
+    assert ei.value.status == P.SL_EINVAL
+
+
+def test_timeout_then_completion(surfaces):
+    """sl_wait with a zero timeout on fresh work reports SL_ETIMEDOUT; the request still
+    completes and a later wait returns it."""
+    import paper_2310_13908_amd as P
+    s = make_surface(RBC, 90)
+    f = sh_force(s.x0, 77)
+    with P.Context(0, hbm_budget_bytes=512 << 20) as c:
+        h = c.register_surface(dev_t(s.X), dev_t(s.w), 2 * math.pi / 91)
+        rid, _ = c.submit(h, dev_t(f), precision="fp64")
+        assert P.sl_wait(c.ptr, rid, 0.0) == P.SL_ETIMEDOUT
+        c.wait(rid, 60.0)
+
+
+def test_kernel_relaunch_after_idle(ctx, surfaces, refs):
+    """The persistent kernel exits after ~250 ms without work; new work relaunches it."""
+    s, f, d = surfaces[0]
+    h = ctx.register_surface(dev_t(s.X), dev_t(s.w), d)
+    rid, _ = ctx.submit(h, dev_t(f), mu=0.8, precision="mixed")
+    ctx.wait(rid)
+    n0 = ctx.stats().kernel_launches
+    time.sleep(0.6)
+    rid, _ = ctx.submit(h, dev_t(f), mu=0.8, precision="mixed")
+    u = ctx.wait(rid).cpu().numpy()
+    assert eps(u, refs[0]) < TOL["mixed"]
+    assert ctx.stats().kernel_launches >= n0 + 1

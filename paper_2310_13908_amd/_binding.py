@@ -51,6 +51,9 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it first "
                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    # torch provides the device memory and streams the library works on; load its HIP runtime
+    # first so that the library binds to the same runtime instance (one libamdhip64 per process).
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, V = ctypes.c_void_p, ctypes.c_void_p
     i64, u64, d, i32 = ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_int

@@ -62,11 +62,12 @@ struct EvalWorkspace {
     SrcOut so;
     TgtOut to;
     double *part;
+    double *part_near;
     void *tblock;
 };
 
 static size_t carve(char *base, EvalWorkspace &w, int64_t n_sort, int64_t np_s, int64_t np_t,
-                    bool distinct, bool mixed, bool vard, int n_splits)
+                    bool distinct, bool mixed, bool vard, int n_splits, int near_ways)
 {
     size_t off = 0;
     auto take = [&](size_t bytes) -> char * {
@@ -95,6 +96,7 @@ static size_t carve(char *base, EvalWorkspace &w, int64_t n_sort, int64_t np_s, 
     }
     if (vard) w.to.delta = (double *)take(np_t * 8);
     w.part = (double *)take((size_t)n_splits * 3 * np_t * 8);
+    w.part_near = (double *)take((size_t)near_ways * 3 * np_t * 8);
     w.tblock = take(tblock_scratch_bytes((int)(np_t / kWave)));   // enough for any R >= 1
     return off;
 }
@@ -265,13 +267,15 @@ sl_status sl_eval(sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *s
         R = ctx->targets_per_lane;
         wps = ctx->waves_per_simd;
     }
-    const PairPlan plan = plan_pairs(np_s, np_t, R, ctx->n_cu * 4 * wps);
+    PairPlan plan = plan_pairs(np_s, np_t, R, ctx->n_cu * 4 * wps);
+    plan.n_cu = ctx->n_cu;
 
     EvalWorkspace ws;
-    const size_t bytes = carve(nullptr, ws, n_sort, np_s, np_t, !same, mixed, vard, plan.n_splits);
+    const size_t bytes = carve(nullptr, ws, n_sort, np_s, np_t, !same, mixed, vard, plan.n_splits,
+                               plan.near_ways);
     char *base = nullptr;
     SL_HIP(hipMallocAsync((void **)&base, bytes, st));
-    carve(base, ws, n_sort, np_s, np_t, !same, mixed, vard, plan.n_splits);
+    carve(base, ws, n_sort, np_s, np_t, !same, mixed, vard, plan.n_splits, plan.near_ways);
 
     hipError_t e = launch_bbox(sx, sy, sz, n_src, tx, ty, tz, same ? 0 : n_tgt, ws.ps, st);
     const uint32_t *order = nullptr;
@@ -311,6 +315,8 @@ sl_status sl_eval(sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *s
     pa.clusters_per_split = plan.clusters_per_split;
     pa.n_splits = plan.n_splits;
     pa.n_tblocks = plan.n_tblocks;
+    pa.near_ways = plan.near_ways;
+    pa.part_near = ws.part_near;
     pa.part = ws.part;
     pa.bbox = ws.ps.bbox;
     pa.tblock_scratch = ws.tblock;
@@ -332,7 +338,8 @@ sl_status sl_eval(sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *s
         ctx->timed.push_back(tev);
     }
     if (e == hipSuccess)
-        e = launch_reduce(ws.part, plan.n_splits, np_t, tv.perm, 1.0 / (8.0 * M_PI * mu), ux, uy, uz, st);
+        e = launch_reduce(ws.part, plan.n_splits, ws.part_near, plan.near_ways, np_t, tv.perm,
+                          1.0 / (8.0 * M_PI * mu), ux, uy, uz, st);
     const hipError_t ef = hipFreeAsync(base, st);
     if (e != hipSuccess) return hip_fail(e, "sl_eval: kernel launch");
     if (ef != hipSuccess) return hip_fail(ef, "sl_eval: hipFreeAsync");

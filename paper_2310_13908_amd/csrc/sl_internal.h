@@ -65,7 +65,9 @@ struct PairArgs {
     int64_t clusters_per_split;
     int n_splits;
     int n_tblocks;
-    double *part;            // [n_splits][3][t.np] partial sums (unscaled)
+    int near_ways;           // K: near clusters of a block are dealt out to K waves by rank
+    double *part;            // [n_splits][3][t.np] far partial sums (unscaled)
+    double *part_near;       // [near_ways][3][t.np] near partial sums (unscaled)
     const double *bbox;      // [6] box of all points (min xyz, max xyz): bounds the rounding
                              // of the single-precision positions in the mixed path
     void *tblock_scratch;    // tblock_scratch_bytes(n_tblocks): per-target-block spheres
@@ -83,14 +85,17 @@ struct PairPlan {
     int n_tblocks;
     int n_splits;
     int64_t clusters_per_split;
+    int near_ways;
+    int n_cu;                // compute units: the work loops launch an occupancy-sized grid
 };
 
 PairPlan plan_pairs(int64_t np_src, int64_t np_tgt, int R, int waves_wanted);
 
 hipError_t launch_pair(const PairArgs &a, const PairPlan &p, bool mixed, bool var_delta,
                        hipStream_t st, const PairTiming *tm);
-hipError_t launch_reduce(const double *part, int n_splits, int64_t np, const int32_t *perm,
-                         double scale, double *ux, double *uy, double *uz, hipStream_t st);
+hipError_t launch_reduce(const double *part, int n_splits, const double *part_near, int near_ways,
+                         int64_t np, const int32_t *perm, double scale, double *ux, double *uy,
+                         double *uz, hipStream_t st);
 hipError_t launch_fill_zero(double *ux, double *uy, double *uz, int64_t n, hipStream_t st);
 
 // ---------------------------------------------------------------------------------------

@@ -30,10 +30,11 @@ namespace sl {
 namespace {
 
 constexpr int kMinClustersPerSplit = 4;
+constexpr int kMaxNearWays = 64;
 
 template <int R>
 __global__ __launch_bounds__(kWave) void k_tblock(PairArgs a, TBlockRec *__restrict__ out,
-                                                  int mixed)
+                                                  int mixed, uint32_t *__restrict__ ctr)
 {
     const int tb = blockIdx.x;
     const int lane = threadIdx.x;
@@ -77,14 +78,27 @@ __global__ __launch_bounds__(kWave) void k_tblock(PairArgs a, TBlockRec *__restr
         rec.gap_far_mixed = gap_far;
         rec.pad0 = rec.pad1 = 0.0;
         out[tb] = rec;
+        if (tb == 0) {          // work counters of k_far and k_near, which run after this kernel
+            ctr[0] = 0u;
+            ctr[1] = 0u;
+        }
     }
 }
 
+// Far clusters of source split `split` against target block `tb`.  The source arrays arrive as
+// separate restrict-qualified kernel arguments: the compiler then knows that the partial-sum
+// stores never alias them and keeps reading them with scalar loads inside the work loop.
 template <int R, bool MIXED>
-__global__ __launch_bounds__(kWave) void k_far(PairArgs a, const TBlockRec *__restrict__ tbr)
+__device__ __forceinline__ void far_item(const PairArgs &a, const TBlockRec *__restrict__ tbr,
+                                         const double *__restrict__ Sx, const double *__restrict__ Sy,
+                                         const double *__restrict__ Sz, const double *__restrict__ Gx,
+                                         const double *__restrict__ Gy, const double *__restrict__ Gz,
+                                         const float *__restrict__ Sx32, const float *__restrict__ Sy32,
+                                         const float *__restrict__ Sz32, const float *__restrict__ Gx32,
+                                         const float *__restrict__ Gy32, const float *__restrict__ Gz32,
+                                         const double4 *__restrict__ sphere, double *__restrict__ part,
+                                         int tb, int split)
 {
-    const int split = (int)(blockIdx.x % (unsigned)a.n_splits);
-    const int tb = (int)(blockIdx.x / (unsigned)a.n_splits);
     const int lane = threadIdx.x;
     const int64_t t0 = (int64_t)tb * (kWave * R);
     const int64_t np_t = a.t.np;
@@ -114,7 +128,7 @@ __global__ __launch_bounds__(kWave) void k_far(PairArgs a, const TBlockRec *__re
     const int64_t c_begin = (int64_t)split * a.clusters_per_split;
     const int64_t c_end = c_begin + a.clusters_per_split < n_cl ? c_begin + a.clusters_per_split : n_cl;
     for (int64_t c = c_begin; c < c_end; ++c) {
-        if (!cluster_is_far(rec, a.s.sphere[c])) continue;
+        if (!cluster_is_far(rec, sphere[c])) continue;
         const int64_t j0 = c * kCluster;
         if constexpr (MIXED) {
             float px[R], py[R], pz[R];
@@ -122,8 +136,8 @@ __global__ __launch_bounds__(kWave) void k_far(PairArgs a, const TBlockRec *__re
             for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
 #pragma unroll 8
             for (int j = 0; j < kCluster; ++j) {
-                const float sx = a.s.x32[j0 + j], sy = a.s.y32[j0 + j], sz = a.s.z32[j0 + j];
-                const float gx = a.s.gx32[j0 + j], gy = a.s.gy32[j0 + j], gz = a.s.gz32[j0 + j];
+                const float sx = Sx32[j0 + j], sy = Sy32[j0 + j], sz = Sz32[j0 + j];
+                const float gx = Gx32[j0 + j], gy = Gy32[j0 + j], gz = Gz32[j0 + j];
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     far_pair32(tx32[r], ty32[r], tz32[r], sx, sy, sz, gx, gy, gz, px[r], py[r], pz[r]);
@@ -137,8 +151,8 @@ __global__ __launch_bounds__(kWave) void k_far(PairArgs a, const TBlockRec *__re
         } else {
 #pragma unroll 4
             for (int j = 0; j < kCluster; ++j) {
-                const double sx = a.s.x[j0 + j], sy = a.s.y[j0 + j], sz = a.s.z[j0 + j];
-                const double gx = a.s.gx[j0 + j], gy = a.s.gy[j0 + j], gz = a.s.gz[j0 + j];
+                const double sx = Sx[j0 + j], sy = Sy[j0 + j], sz = Sz[j0 + j];
+                const double gx = Gx[j0 + j], gy = Gy[j0 + j], gz = Gz[j0 + j];
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     far_pair64(tx[r], ty[r], tz[r], sx, sy, sz, gx, gy, gz, ax[r], ay[r], az[r]);
@@ -146,9 +160,9 @@ __global__ __launch_bounds__(kWave) void k_far(PairArgs a, const TBlockRec *__re
         }
     }
 
-    double *px = a.part + ((int64_t)split * 3 + 0) * np_t;
-    double *py = a.part + ((int64_t)split * 3 + 1) * np_t;
-    double *pz = a.part + ((int64_t)split * 3 + 2) * np_t;
+    double *px = part + ((int64_t)split * 3 + 0) * np_t;
+    double *py = part + ((int64_t)split * 3 + 1) * np_t;
+    double *pz = part + ((int64_t)split * 3 + 2) * np_t;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t i = t0 + r * kWave + lane;
@@ -164,22 +178,52 @@ __global__ __launch_bounds__(kWave) void k_far(PairArgs a, const TBlockRec *__re
     }
 }
 
-template <int R, bool VARD>
-__global__ __launch_bounds__(kWave) void k_near(PairArgs a, const TBlockRec *__restrict__ tbr)
+// Next work item of a wave (lane 0 draws from the counter; the index is made wave-uniform).
+__device__ __forceinline__ uint32_t next_item(uint32_t *__restrict__ ctr)
 {
-    const int split = (int)(blockIdx.x % (unsigned)a.n_splits);
-    const int tb = (int)(blockIdx.x / (unsigned)a.n_splits);
+    uint32_t v = 0;
+    if (threadIdx.x == 0) v = atomicAdd(ctr, 1u);
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Occupancy-sized grid; every wave pulls (split, target block) items until none are left.
+// Items are split-major, so the waves working at the same time share one source split in L2.
+template <int R, bool MIXED>
+__global__ __launch_bounds__(kWave) void k_far(PairArgs a, const TBlockRec *__restrict__ tbr,
+                                               const double *__restrict__ Sx, const double *__restrict__ Sy,
+                                               const double *__restrict__ Sz, const double *__restrict__ Gx,
+                                               const double *__restrict__ Gy, const double *__restrict__ Gz,
+                                               const float *__restrict__ Sx32, const float *__restrict__ Sy32,
+                                               const float *__restrict__ Sz32, const float *__restrict__ Gx32,
+                                               const float *__restrict__ Gy32, const float *__restrict__ Gz32,
+                                               const double4 *__restrict__ sphere, double *__restrict__ part,
+                                               uint32_t *__restrict__ ctr)
+{
+    const uint32_t n_items = (uint32_t)a.n_tblocks * (uint32_t)a.n_splits;
+    for (uint32_t item = next_item(ctr); item < n_items; item = next_item(ctr)) {
+        const int tb = (int)(item % (uint32_t)a.n_tblocks);
+        const int split = (int)(item / (uint32_t)a.n_tblocks);
+        far_item<R, MIXED>(a, tbr, Sx, Sy, Sz, Gx, Gy, Gz, Sx32, Sy32, Sz32, Gx32, Gy32, Gz32,
+                           sphere, part, tb, split);
+    }
+}
+
+// Near clusters of a target block are few and contiguous in the sorted order, so they are dealt
+// out by rank instead of by source range: wave (tb, k) scans all clusters 64 at a time (one per
+// lane), and takes the near clusters whose rank among the block's near clusters is k mod K.
+template <int R, bool VARD>
+__device__ __forceinline__ void near_item(const PairArgs &a, const TBlockRec *__restrict__ tbr,
+                                          const double *__restrict__ Sx, const double *__restrict__ Sy,
+                                          const double *__restrict__ Sz, const double *__restrict__ Gx,
+                                          const double *__restrict__ Gy, const double *__restrict__ Gz,
+                                          const double4 *__restrict__ sphere,
+                                          double *__restrict__ part_near, int tb, int k)
+{
+    const int K = a.near_ways;
     const int lane = threadIdx.x;
     const int64_t t0 = (int64_t)tb * (kWave * R);
     const int64_t np_t = a.t.np;
     const TBlockRec rec = tbr[tb];
-
-    const int64_t n_cl = a.s.np / kCluster;
-    const int64_t c_begin = (int64_t)split * a.clusters_per_split;
-    const int64_t c_end = c_begin + a.clusters_per_split < n_cl ? c_begin + a.clusters_per_split : n_cl;
-    int64_t c = c_begin;
-    while (c < c_end && cluster_is_far(rec, a.s.sphere[c])) ++c;
-    if (c == c_end) return;                         // nothing near in this split
 
     double tx[R], ty[R], tz[R], ax[R], ay[R], az[R];
     DeltaC dcv[R];
@@ -194,33 +238,60 @@ __global__ __launch_bounds__(kWave) void k_near(PairArgs a, const TBlockRec *__r
     }
     const DeltaC dcu = make_delta(a.delta);
 
-    for (; c < c_end; ++c) {
-        if (cluster_is_far(rec, a.s.sphere[c])) continue;
-        const int64_t j0 = c * kCluster;
+    const int64_t n_cl = a.s.np / kCluster;
+    uint32_t rank = 0;
+    for (int64_t c0 = 0; c0 < n_cl; c0 += kWave) {
+        const int64_t cl = c0 + lane;
+        const bool near = cl < n_cl && !cluster_is_far(rec, sphere[cl]);
+        uint64_t mask = __ballot(near);
+        while (mask) {
+            const int b = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            if ((int)(rank++ % (uint32_t)K) != k) continue;
+            const int64_t j0 = (c0 + b) * kCluster;
 #pragma unroll 1
-        for (int j = 0; j < kCluster; ++j) {
-            const double sx = a.s.x[j0 + j], sy = a.s.y[j0 + j], sz = a.s.z[j0 + j];
-            const double gx = a.s.gx[j0 + j], gy = a.s.gy[j0 + j], gz = a.s.gz[j0 + j];
+            for (int j = 0; j < kCluster; ++j) {
+                const double sx = Sx[j0 + j], sy = Sy[j0 + j], sz = Sz[j0 + j];
+                const double gx = Gx[j0 + j], gy = Gy[j0 + j], gz = Gz[j0 + j];
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-                near_pair64(tx[r], ty[r], tz[r], sx, sy, sz, gx, gy, gz, VARD ? dcv[r] : dcu,
-                            ax[r], ay[r], az[r]);
+                for (int r = 0; r < R; ++r)
+                    near_pair64(tx[r], ty[r], tz[r], sx, sy, sz, gx, gy, gz, VARD ? dcv[r] : dcu,
+                                ax[r], ay[r], az[r]);
+            }
         }
     }
 
-    double *px = a.part + ((int64_t)split * 3 + 0) * np_t;
-    double *py = a.part + ((int64_t)split * 3 + 1) * np_t;
-    double *pz = a.part + ((int64_t)split * 3 + 2) * np_t;
+    double *px = part_near + ((int64_t)k * 3 + 0) * np_t;
+    double *py = part_near + ((int64_t)k * 3 + 1) * np_t;
+    double *pz = part_near + ((int64_t)k * 3 + 2) * np_t;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t i = t0 + r * kWave + lane;
-        px[i] += ax[r];
-        py[i] += ay[r];
-        pz[i] += az[r];
+        px[i] = ax[r];
+        py[i] = ay[r];
+        pz[i] = az[r];
     }
 }
 
+// Occupancy-sized grid pulling (target block, way) items, block-major so that the waves of one
+// block (which read the same near sources) run together.
+template <int R, bool VARD>
+__global__ __launch_bounds__(kWave) void k_near(PairArgs a, const TBlockRec *__restrict__ tbr,
+                                                const double *__restrict__ Sx, const double *__restrict__ Sy,
+                                                const double *__restrict__ Sz, const double *__restrict__ Gx,
+                                                const double *__restrict__ Gy, const double *__restrict__ Gz,
+                                                const double4 *__restrict__ sphere,
+                                                double *__restrict__ part_near, uint32_t *__restrict__ ctr)
+{
+    const uint32_t n_items = (uint32_t)a.n_tblocks * (uint32_t)a.near_ways;
+    for (uint32_t item = next_item(ctr); item < n_items; item = next_item(ctr))
+        near_item<R, VARD>(a, tbr, Sx, Sy, Sz, Gx, Gy, Gz, sphere, part_near,
+                           (int)(item / (uint32_t)a.near_ways), (int)(item % (uint32_t)a.near_ways));
+}
+
+// Per target: far partials of the source splits, then near partials of the K ways, in order.
 __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ part, int n_splits,
+                                                const double *__restrict__ part_near, int near_ways,
                                                 int64_t np, const int32_t *__restrict__ perm,
                                                 double scale, double *__restrict__ ux,
                                                 double *__restrict__ uy, double *__restrict__ uz)
@@ -235,6 +306,11 @@ __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ part,
         b += part[((int64_t)s * 3 + 1) * np + p];
         c += part[((int64_t)s * 3 + 2) * np + p];
     }
+    for (int s = 0; s < near_ways; ++s) {
+        a += part_near[((int64_t)s * 3 + 0) * np + p];
+        b += part_near[((int64_t)s * 3 + 1) * np + p];
+        c += part_near[((int64_t)s * 3 + 2) * np + p];
+    }
     ux[idx] = a * scale;
     uy[idx] = b * scale;
     uz[idx] = c * scale;
@@ -247,30 +323,63 @@ __global__ __launch_bounds__(256) void k_fill_zero(double *__restrict__ ux, doub
     if (i < n) { ux[i] = 0.0; uy[i] = 0.0; uz[i] = 0.0; }
 }
 
+// Resident wavefronts per CU of a kernel (queried once per kernel instance).
+template <typename K>
+int resident_waves(K kernel)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)kernel, kWave, 0) != hipSuccess ||
+        nb < 1)
+        nb = 4;
+    return nb;
+}
+
+template <typename K>
+unsigned work_grid(K kernel, int &cache, int n_cu, int64_t n_items)
+{
+    if (cache == 0) cache = resident_waves(kernel);
+    const int64_t g = (int64_t)n_cu * cache;
+    return (unsigned)(g < n_items ? g : n_items);
+}
+
 template <int R>
 hipError_t launch_r(const PairArgs &a, const PairPlan &p, bool mixed, bool vard, hipStream_t st,
                     const PairTiming *tm)
 {
-    const unsigned grid = (unsigned)((int64_t)p.n_tblocks * p.n_splits);
+    static int occ_far[2] = {0, 0}, occ_near[2] = {0, 0};
     TBlockRec *rec = reinterpret_cast<TBlockRec *>(a.tblock_scratch);
-    hipLaunchKernelGGL((k_tblock<R>), dim3(p.n_tblocks), dim3(kWave), 0, st, a, rec, (int)mixed);
+    uint32_t *ctr = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(a.tblock_scratch) +
+                                                 tblock_scratch_bytes(p.n_tblocks) - 256);
+    const SrcView &s = a.s;
+    hipLaunchKernelGGL((k_tblock<R>), dim3(p.n_tblocks), dim3(kWave), 0, st, a, rec, (int)mixed, ctr);
     if (tm && tm->e0) (void)hipEventRecord(tm->e0, st);
+    const int64_t n_far = (int64_t)p.n_tblocks * p.n_splits;
     if (mixed)
-        hipLaunchKernelGGL((k_far<R, true>), dim3(grid), dim3(kWave), 0, st, a, rec);
+        hipLaunchKernelGGL((k_far<R, true>), dim3(work_grid(k_far<R, true>, occ_far[1], p.n_cu, n_far)),
+                           dim3(kWave), 0, st, a, rec, s.x, s.y, s.z, s.gx, s.gy, s.gz, s.x32, s.y32,
+                           s.z32, s.gx32, s.gy32, s.gz32, s.sphere, a.part, ctr);
     else
-        hipLaunchKernelGGL((k_far<R, false>), dim3(grid), dim3(kWave), 0, st, a, rec);
+        hipLaunchKernelGGL((k_far<R, false>), dim3(work_grid(k_far<R, false>, occ_far[0], p.n_cu, n_far)),
+                           dim3(kWave), 0, st, a, rec, s.x, s.y, s.z, s.gx, s.gy, s.gz, s.x32, s.y32,
+                           s.z32, s.gx32, s.gy32, s.gz32, s.sphere, a.part, ctr);
     if (tm && tm->e1) (void)hipEventRecord(tm->e1, st);
+    const int64_t n_near = (int64_t)p.n_tblocks * p.near_ways;
     if (vard)
-        hipLaunchKernelGGL((k_near<R, true>), dim3(grid), dim3(kWave), 0, st, a, rec);
+        hipLaunchKernelGGL((k_near<R, true>), dim3(work_grid(k_near<R, true>, occ_near[1], p.n_cu, n_near)),
+                           dim3(kWave), 0, st, a, rec, s.x, s.y, s.z, s.gx, s.gy, s.gz, s.sphere,
+                           a.part_near, ctr + 1);
     else
-        hipLaunchKernelGGL((k_near<R, false>), dim3(grid), dim3(kWave), 0, st, a, rec);
+        hipLaunchKernelGGL((k_near<R, false>), dim3(work_grid(k_near<R, false>, occ_near[0], p.n_cu, n_near)),
+                           dim3(kWave), 0, st, a, rec, s.x, s.y, s.z, s.gx, s.gy, s.gz, s.sphere,
+                           a.part_near, ctr + 1);
     if (tm && tm->e2) (void)hipEventRecord(tm->e2, st);
     return hipGetLastError();
 }
 
 }  // namespace
 
-size_t tblock_scratch_bytes(int n_tblocks) { return (size_t)n_tblocks * sizeof(TBlockRec); }
+// Target-block records followed by 256 bytes holding the two work counters.
+size_t tblock_scratch_bytes(int n_tblocks) { return (size_t)n_tblocks * sizeof(TBlockRec) + 256; }
 
 PairPlan plan_pairs(int64_t np_src, int64_t np_tgt, int R, int waves_wanted)
 {
@@ -283,6 +392,10 @@ PairPlan plan_pairs(int64_t np_src, int64_t np_tgt, int R, int waves_wanted)
     S = S < 1 ? 1 : (S > smax ? smax : S);
     p.clusters_per_split = (n_cl + S - 1) / S;
     p.n_splits = (int)((n_cl + p.clusters_per_split - 1) / p.clusters_per_split);
+    int64_t K = (waves_wanted + p.n_tblocks - 1) / p.n_tblocks;
+    K = K < 1 ? 1 : (K > kMaxNearWays ? kMaxNearWays : K);
+    K = K > n_cl ? n_cl : K;
+    p.near_ways = (int)K;
     return p;
 }
 
@@ -297,11 +410,12 @@ hipError_t launch_pair(const PairArgs &a, const PairPlan &p, bool mixed, bool va
     }
 }
 
-hipError_t launch_reduce(const double *part, int n_splits, int64_t np, const int32_t *perm,
-                         double scale, double *ux, double *uy, double *uz, hipStream_t st)
+hipError_t launch_reduce(const double *part, int n_splits, const double *part_near, int near_ways,
+                         int64_t np, const int32_t *perm, double scale, double *ux, double *uy,
+                         double *uz, hipStream_t st)
 {
     hipLaunchKernelGGL(k_reduce, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, part,
-                       n_splits, np, perm, scale, ux, uy, uz);
+                       n_splits, part_near, near_ways, np, perm, scale, ux, uy, uz);
     return hipGetLastError();
 }
 

@@ -45,10 +45,12 @@ typedef enum {
 
 typedef enum {
     SL_FP64 = 0,        /* every pair in double precision; ~1e-15 relative to the exact sum */
-    SL_MIXED = 1        /* far pairs in single precision with two-sum compensated per-target
-                           accumulation; pairs near the target (rho = r/delta below the FP64
-                           cut, default 5), the self term and the final per-target sum in
-                           double precision; ~1e-7 relative */
+    SL_MIXED = 1        /* pairs with rho = r/delta >= rho64 in single precision (smoothed for
+                           rho < 5, plain Stokeslet beyond, where s1 = s2 = 1 to single
+                           precision), summed per cluster of 64 sources and folded into a
+                           per-target two-sum (hi, lo) pair; pairs with rho < rho64 (default 1:
+                           the self term and the nearest neighbours, where s2 cancels) and the
+                           final per-target sum in double precision; ~1e-7 relative */
 } sl_precision;
 
 typedef struct sl_ctx sl_ctx;   /* opaque; one per device */
@@ -69,8 +71,8 @@ const char *sl_last_error(void);
 
 /* Tunables.
  * SL_PARAM_RHO64: in SL_MIXED, pairs with r/delta below this value are summed in double
- *   precision (the single-precision zone needs r/delta >= 5, where s1 = s2 = 1 to single
- *   precision; values below 5 are rejected).  Default 5.
+ *   precision (finite, >= 0.5; default 1).  Serving requests take the value current at
+ *   sl_submit.
  * SL_PARAM_KERNEL_TIMING: 1 = bracket every pair-kernel launch of sl_eval with HIP events on
  *   the caller's stream and accumulate the elapsed time into sl_stats; 0 (default) = off.
  * SL_PARAM_TARGETS_PER_LANE: targets each lane of the pair kernel keeps in registers

@@ -37,6 +37,10 @@ G_LO, G_HI = 0.5, 6.9   # range of the g fit (p)
 G_K = 3.0               # t = G_K / (G_K + p)
 G_DEG = 16
 EXP_DEG = 13            # Taylor degree of e^x on |x| <= ln2/2
+# Single-precision smoothing of the mixed path (0.5 <= p < 5): g as a polynomial in
+# t - G32_MID, t = G_K / (G_K + p), coefficients rounded to single precision.
+G32_LO, G32_HI = 0.5, 5.0
+G32_DEG = 7
 
 
 def series_coeffs():
@@ -60,6 +64,25 @@ def g_coeffs():
     A = mp.matrix([[t ** i for i in range(G_DEG + 1)] for t in ts])
     y = mp.matrix([g_exact(G_K / t - G_K) for t in ts])
     return [c for c in mp.lu_solve(A, y)]
+
+
+def g32_coeffs():
+    ta, tb = G_K / (G_K + G32_HI), G_K / (G_K + G32_LO)
+    mid = float(np.float32((ta + tb) / 2))
+    nodes = [mp.cos(mp.pi * (j + mp.mpf(1) / 2) / (G32_DEG + 1)) for j in range(G32_DEG + 1)]
+    ts = [mp.mpf((ta + tb) / 2) + mp.mpf((tb - ta) / 2) * c for c in nodes]
+    A = mp.matrix([[(t - mp.mpf(mid)) ** i for i in range(G32_DEG + 1)] for t in ts])
+    y = mp.matrix([g_exact(G_K / t - G_K) for t in ts])
+    cf = [float(np.float32(float(c))) for c in mp.lu_solve(A, y)]
+    # error of the single-precision evaluation (numpy float32 mirrors the device arithmetic)
+    p = np.linspace(G32_LO, G32_HI, 2001)
+    t = (np.float32(G_K) * (np.float32(1) / (np.float32(G_K) + p.astype(np.float32)))).astype(np.float32)
+    t = (t - np.float32(mid)).astype(np.float32)
+    v = np.full_like(t, np.float32(cf[-1]))
+    for c in cf[-2::-1]:
+        v = (v * t + np.float32(c)).astype(np.float32)
+    err = max(float(abs(mp.mpf(float(a)) - g_exact(float(x)))) for x, a in zip(p[::4], v[::4]))
+    return cf, mid, err
 
 
 def horner(cf, x):
@@ -118,6 +141,8 @@ def main():
     gc = g_coeffs()
     hi, lo = ln2_split()
     rep = check(c1, c2, gc)
+    g32, g32_mid, g32_err = g32_coeffs()
+    rep["g32_abs"] = g32_err
     for k, v in rep.items():
         print(f"{k}: {v:.3e}")
     lines = [
@@ -144,6 +169,11 @@ def main():
         f"constexpr double kLn2Hi = {hi!r};",
         f"constexpr double kLn2Lo = {lo!r};",
         f"constexpr double kLog2E = {float(1 / mp.log(2))!r};",
+        f"// single precision (mixed path), 0.5 <= p < 5, g abs error {g32_err:.2e}:",
+        f"// g(p) ~= sum kG32[i] (t - kG32Mid)^i, t = kGK / (kGK + p)",
+        f"constexpr int kG32Deg = {G32_DEG};",
+        f"constexpr float kG32Mid = {g32_mid!r}f;",
+        "constexpr float kG32[kG32Deg + 1] = {" + ", ".join(f"{c:.9e}f" for c in g32) + "};",
         "}  // namespace sl",
         "",
     ]

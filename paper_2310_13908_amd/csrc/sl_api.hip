@@ -137,8 +137,8 @@ sl_status sl_set_param(sl_ctx *ctx, sl_param key, double value)
 {
     if (!ctx) return fail(SL_EINVAL, "sl_set_param: ctx is NULL");
     if (key == SL_PARAM_RHO64) {
-        if (!isfinite(value) || value < kRhoExact32)
-            return fail(SL_EINVAL, "sl_set_param: rho64 must be finite and >= 5");
+        if (!isfinite(value) || value < kRho64Min)
+            return fail(SL_EINVAL, "sl_set_param: rho64 must be finite and >= 0.5");
         std::lock_guard<std::mutex> l(ctx->mu);
         ctx->rho64 = value;
         return SL_OK;
@@ -311,7 +311,12 @@ sl_status sl_eval(sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *s
                    ws.so.sphere, np_s};
     pa.t = tv;
     pa.delta = vard ? 1.0 : delta;
-    pa.far_cut = mixed ? ctx->rho64 : kRhoExact64;
+    {
+        std::lock_guard<std::mutex> l(ctx->mu);
+        pa.rho64 = ctx->rho64;
+    }
+    // far clusters: s = 1 to the working precision, and (mixed) outside the FP64 zone
+    pa.far_cut = mixed ? std::max(kRhoExact32, pa.rho64) : kRhoExact64;
     pa.clusters_per_split = plan.clusters_per_split;
     pa.n_splits = plan.n_splits;
     pa.n_tblocks = plan.n_tblocks;

@@ -25,6 +25,8 @@ constexpr int kPad = 256;            // point arrays are padded to a multiple of
 constexpr double kC0 = 0.376126389031837524632052967707181724;   // 2 / (3 sqrt(pi))
 constexpr double kRhoExact64 = 6.9;  // s1 = s2 = 1 in double precision beyond this r/delta
 constexpr double kRhoExact32 = 5.0;  // ... and in single precision beyond this r/delta
+constexpr double kRho64Min = 0.5;    // smallest double-precision zone of the mixed path (the
+                                     // single-precision smoothing is fitted on 0.5 <= p < 5)
 
 // 1/sqrt(x) for finite x > 0 to ~1 ulp: hardware estimate (good to about 2^-23 relative)
 // refined by one third-order step y (1 + e/2 + 3e^2/8), e = 1 - x y^2.
@@ -153,6 +155,71 @@ __device__ __forceinline__ void near_pair64(double tx, double ty, double tz,
     ax = fma(K1, gx, fma(c, dx, ax));
     ay = fma(K1, gy, fma(c, dy, ay));
     az = fma(K1, gz, fma(c, dz, az));
+}
+
+// Single-precision constants of the mixed path's near zone for one target: 1/delta, 1/delta^2,
+// and the squared radii of its double-precision zone (rho64 delta)^2 and of the smoothing
+// (5 delta)^2.
+struct DeltaC32 {
+    float id, id2, cut2_64, cut2_5;
+};
+
+__device__ __forceinline__ DeltaC32 make_delta32(double delta, double rho64)
+{
+    DeltaC32 c;
+    c.id = (float)(1.0 / delta);
+    c.id2 = (float)(1.0 / (delta * delta));
+    c.cut2_64 = (float)(rho64 * rho64 * delta * delta);
+    c.cut2_5 = (float)(kRhoExact32 * kRhoExact32 * delta * delta);
+    return c;
+}
+
+// Smoothed K1 = s1(p)/r, K2 = s2(p)/r^3 in single precision for 0.5 <= p < 5 (no cancellation
+// there: s1 >= 1.5 p, s2 >= 0.55): s = 1 - e^{-q} (g(p) + P(p)) as in smoothing64, with the
+// hardware exp2 and reciprocal and a degree-7 fit of g.
+__device__ __forceinline__ void smoothing32(float r2, float ri, const DeltaC32 &dc, float &K1,
+                                            float &K2)
+{
+    const float q = r2 * dc.id2;
+    const float p = (r2 * ri) * dc.id;
+    const float E = __builtin_amdgcn_exp2f(-q * 1.44269504088896340736f);
+    const float t = (float)kGK * __builtin_amdgcn_rcpf((float)kGK + p) - kG32Mid;
+    float g = kG32[kG32Deg];
+#pragma unroll
+    for (int i = kG32Deg - 1; i >= 0; --i) g = fmaf(g, t, kG32[i]);
+    const float c0p = (float)kC0 * p;
+    const float A1 = fmaf(c0p, fmaf(2.0f, q, -5.0f), g);
+    const float A2 = fmaf(c0p, fmaf(q, fmaf(4.0f, q, -14.0f), 3.0f), g);
+    K1 = ri * fmaf(-E, A1, 1.0f);
+    K2 = (ri * ri * ri) * fmaf(-E, A2, 1.0f);
+}
+
+// Near pair of the mixed path.  p < rho64 (including r = 0): the double-precision kernel,
+// accumulated in (ax, ay, az).  rho64 <= p < 5: smoothed kernel in single precision; p >= 5:
+// plain Stokeslet in single precision; both accumulated in (px, py, pz).  The zone is decided
+// from the single-precision distance.
+__device__ __forceinline__ void near_pair_mixed(float tx32, float ty32, float tz32, double tx,
+                                                double ty, double tz, float sx32, float sy32,
+                                                float sz32, float gx32, float gy32, float gz32,
+                                                double sx, double sy, double sz, double gx,
+                                                double gy, double gz, const DeltaC &dc64,
+                                                const DeltaC32 &dc32, float &px, float &py,
+                                                float &pz, double &ax, double &ay, double &az)
+{
+    const float dx = tx32 - sx32, dy = ty32 - sy32, dz = tz32 - sz32;
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    if (r2 < dc32.cut2_64) {
+        near_pair64(tx, ty, tz, sx, sy, sz, gx, gy, gz, dc64, ax, ay, az);
+    } else {
+        const float ri = __builtin_amdgcn_rsqf(r2);
+        float K1 = ri, K2 = ri * ri * ri;
+        if (r2 < dc32.cut2_5) smoothing32(r2, ri, dc32, K1, K2);
+        const float gd = fmaf(gx32, dx, fmaf(gy32, dy, gz32 * dz));
+        const float c = gd * K2;
+        px = fmaf(K1, gx32, fmaf(c, dx, px));
+        py = fmaf(K1, gy32, fmaf(c, dy, py));
+        pz = fmaf(K1, gz32, fmaf(c, dz, pz));
+    }
 }
 
 // Plain Stokeslet pair in single precision (far zone of the mixed path).

@@ -62,6 +62,7 @@ struct PairArgs {
     TgtView t;
     double delta;            // scalar delta when t.delta == nullptr
     double far_cut;          // cluster far test: gap >= far_cut * delta_max
+    double rho64;            // mixed path: pairs with r/delta below this are summed in FP64
     int64_t clusters_per_split;
     int n_splits;
     int n_tblocks;
@@ -165,7 +166,7 @@ struct sl_ctx {
     int device = 0;
     int n_cu = 0;
     size_t budget = 0;
-    double rho64 = sl::kRhoExact32;
+    double rho64 = 1.0;
     int targets_per_lane = 2;
     int waves_per_simd = 4;
     std::mutex mu;

@@ -211,11 +211,17 @@ __global__ __launch_bounds__(kWave) void k_far(PairArgs a, const TBlockRec *__re
 // Near clusters of a target block are few and contiguous in the sorted order, so they are dealt
 // out by rank instead of by source range: wave (tb, k) scans all clusters 64 at a time (one per
 // lane), and takes the near clusters whose rank among the block's near clusters is k mod K.
-template <int R, bool VARD>
+// FP64 path: every pair in double precision.  Mixed path: near_pair_mixed (double precision only
+// below rho64 delta); single-precision terms are summed per cluster and folded into a two-sum
+// (hi, lo) pair per target, as in the far kernel.
+template <int R, bool VARD, bool MIXED>
 __device__ __forceinline__ void near_item(const PairArgs &a, const TBlockRec *__restrict__ tbr,
                                           const double *__restrict__ Sx, const double *__restrict__ Sy,
                                           const double *__restrict__ Sz, const double *__restrict__ Gx,
                                           const double *__restrict__ Gy, const double *__restrict__ Gz,
+                                          const float *__restrict__ Sx32, const float *__restrict__ Sy32,
+                                          const float *__restrict__ Sz32, const float *__restrict__ Gx32,
+                                          const float *__restrict__ Gy32, const float *__restrict__ Gz32,
                                           const double4 *__restrict__ sphere,
                                           double *__restrict__ part_near, int tb, int k)
 {
@@ -226,17 +232,29 @@ __device__ __forceinline__ void near_item(const PairArgs &a, const TBlockRec *__
     const TBlockRec rec = tbr[tb];
 
     double tx[R], ty[R], tz[R], ax[R], ay[R], az[R];
+    float tx32[R], ty32[R], tz32[R], hx[R], hy[R], hz[R], lx[R], ly[R], lz[R];
     DeltaC dcv[R];
+    DeltaC32 dcv32[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t i = t0 + r * kWave + lane;
         tx[r] = a.t.x[i];
         ty[r] = a.t.y[i];
         tz[r] = a.t.z[i];
-        if constexpr (VARD) dcv[r] = make_delta(a.t.delta[i]);
+        if constexpr (VARD) {
+            dcv[r] = make_delta(a.t.delta[i]);
+            if constexpr (MIXED) dcv32[r] = make_delta32(a.t.delta[i], a.rho64);
+        }
+        if constexpr (MIXED) {
+            tx32[r] = a.t.x32[i];
+            ty32[r] = a.t.y32[i];
+            tz32[r] = a.t.z32[i];
+        }
         ax[r] = ay[r] = az[r] = 0.0;
+        hx[r] = hy[r] = hz[r] = lx[r] = ly[r] = lz[r] = 0.0f;
     }
     const DeltaC dcu = make_delta(a.delta);
+    const DeltaC32 dcu32 = make_delta32(a.delta, a.rho64);
 
     const int64_t n_cl = a.s.np / kCluster;
     uint32_t rank = 0;
@@ -249,14 +267,39 @@ __device__ __forceinline__ void near_item(const PairArgs &a, const TBlockRec *__
             mask &= mask - 1;
             if ((int)(rank++ % (uint32_t)K) != k) continue;
             const int64_t j0 = (c0 + b) * kCluster;
-#pragma unroll 1
-            for (int j = 0; j < kCluster; ++j) {
-                const double sx = Sx[j0 + j], sy = Sy[j0 + j], sz = Sz[j0 + j];
-                const double gx = Gx[j0 + j], gy = Gy[j0 + j], gz = Gz[j0 + j];
+            if constexpr (MIXED) {
+                float px[R], py[R], pz[R];
 #pragma unroll
-                for (int r = 0; r < R; ++r)
-                    near_pair64(tx[r], ty[r], tz[r], sx, sy, sz, gx, gy, gz, VARD ? dcv[r] : dcu,
-                                ax[r], ay[r], az[r]);
+                for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
+#pragma unroll 1
+                for (int j = 0; j < kCluster; ++j) {
+                    const float sx32 = Sx32[j0 + j], sy32 = Sy32[j0 + j], sz32 = Sz32[j0 + j];
+                    const float gx32 = Gx32[j0 + j], gy32 = Gy32[j0 + j], gz32 = Gz32[j0 + j];
+                    const double sx = Sx[j0 + j], sy = Sy[j0 + j], sz = Sz[j0 + j];
+                    const double gx = Gx[j0 + j], gy = Gy[j0 + j], gz = Gz[j0 + j];
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        near_pair_mixed(tx32[r], ty32[r], tz32[r], tx[r], ty[r], tz[r], sx32, sy32,
+                                        sz32, gx32, gy32, gz32, sx, sy, sz, gx, gy, gz,
+                                        VARD ? dcv[r] : dcu, VARD ? dcv32[r] : dcu32, px[r], py[r],
+                                        pz[r], ax[r], ay[r], az[r]);
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    two_sum_acc(px[r], hx[r], lx[r]);
+                    two_sum_acc(py[r], hy[r], ly[r]);
+                    two_sum_acc(pz[r], hz[r], lz[r]);
+                }
+            } else {
+#pragma unroll 1
+                for (int j = 0; j < kCluster; ++j) {
+                    const double sx = Sx[j0 + j], sy = Sy[j0 + j], sz = Sz[j0 + j];
+                    const double gx = Gx[j0 + j], gy = Gy[j0 + j], gz = Gz[j0 + j];
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        near_pair64(tx[r], ty[r], tz[r], sx, sy, sz, gx, gy, gz, VARD ? dcv[r] : dcu,
+                                    ax[r], ay[r], az[r]);
+                }
             }
         }
     }
@@ -267,26 +310,30 @@ __device__ __forceinline__ void near_item(const PairArgs &a, const TBlockRec *__
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t i = t0 + r * kWave + lane;
-        px[i] = ax[r];
-        py[i] = ay[r];
-        pz[i] = az[r];
+        px[i] = ax[r] + ((double)hx[r] + (double)lx[r]);
+        py[i] = ay[r] + ((double)hy[r] + (double)ly[r]);
+        pz[i] = az[r] + ((double)hz[r] + (double)lz[r]);
     }
 }
 
 // Occupancy-sized grid pulling (target block, way) items, block-major so that the waves of one
 // block (which read the same near sources) run together.
-template <int R, bool VARD>
+template <int R, bool VARD, bool MIXED>
 __global__ __launch_bounds__(kWave) void k_near(PairArgs a, const TBlockRec *__restrict__ tbr,
                                                 const double *__restrict__ Sx, const double *__restrict__ Sy,
                                                 const double *__restrict__ Sz, const double *__restrict__ Gx,
                                                 const double *__restrict__ Gy, const double *__restrict__ Gz,
+                                                const float *__restrict__ Sx32, const float *__restrict__ Sy32,
+                                                const float *__restrict__ Sz32, const float *__restrict__ Gx32,
+                                                const float *__restrict__ Gy32, const float *__restrict__ Gz32,
                                                 const double4 *__restrict__ sphere,
                                                 double *__restrict__ part_near, uint32_t *__restrict__ ctr)
 {
     const uint32_t n_items = (uint32_t)a.n_tblocks * (uint32_t)a.near_ways;
     for (uint32_t item = next_item(ctr); item < n_items; item = next_item(ctr))
-        near_item<R, VARD>(a, tbr, Sx, Sy, Sz, Gx, Gy, Gz, sphere, part_near,
-                           (int)(item / (uint32_t)a.near_ways), (int)(item % (uint32_t)a.near_ways));
+        near_item<R, VARD, MIXED>(a, tbr, Sx, Sy, Sz, Gx, Gy, Gz, Sx32, Sy32, Sz32, Gx32, Gy32, Gz32,
+                                  sphere, part_near, (int)(item / (uint32_t)a.near_ways),
+                                  (int)(item % (uint32_t)a.near_ways));
 }
 
 // Per target: far partials of the source splits, then near partials of the K ways, in order.
@@ -346,7 +393,7 @@ template <int R>
 hipError_t launch_r(const PairArgs &a, const PairPlan &p, bool mixed, bool vard, hipStream_t st,
                     const PairTiming *tm)
 {
-    static int occ_far[2] = {0, 0}, occ_near[2] = {0, 0};
+    static int occ_far[2] = {0, 0}, occ_near[4] = {0, 0, 0, 0};
     TBlockRec *rec = reinterpret_cast<TBlockRec *>(a.tblock_scratch);
     uint32_t *ctr = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(a.tblock_scratch) +
                                                  tblock_scratch_bytes(p.n_tblocks) - 256);
@@ -364,14 +411,16 @@ hipError_t launch_r(const PairArgs &a, const PairPlan &p, bool mixed, bool vard,
                            s.z32, s.gx32, s.gy32, s.gz32, s.sphere, a.part, ctr);
     if (tm && tm->e1) (void)hipEventRecord(tm->e1, st);
     const int64_t n_near = (int64_t)p.n_tblocks * p.near_ways;
-    if (vard)
-        hipLaunchKernelGGL((k_near<R, true>), dim3(work_grid(k_near<R, true>, occ_near[1], p.n_cu, n_near)),
-                           dim3(kWave), 0, st, a, rec, s.x, s.y, s.z, s.gx, s.gy, s.gz, s.sphere,
-                           a.part_near, ctr + 1);
-    else
-        hipLaunchKernelGGL((k_near<R, false>), dim3(work_grid(k_near<R, false>, occ_near[0], p.n_cu, n_near)),
-                           dim3(kWave), 0, st, a, rec, s.x, s.y, s.z, s.gx, s.gy, s.gz, s.sphere,
-                           a.part_near, ctr + 1);
+#define SL_NEAR_LAUNCH(V, M, SLOT)                                                                  \
+    hipLaunchKernelGGL((k_near<R, V, M>), dim3(work_grid(k_near<R, V, M>, occ_near[SLOT], p.n_cu, n_near)), \
+                       dim3(kWave), 0, st, a, rec, s.x, s.y, s.z, s.gx, s.gy, s.gz, s.x32, s.y32, s.z32, \
+                       s.gx32, s.gy32, s.gz32, s.sphere, a.part_near, ctr + 1)
+    if (vard) {
+        if (mixed) SL_NEAR_LAUNCH(true, true, 3); else SL_NEAR_LAUNCH(true, false, 1);
+    } else {
+        if (mixed) SL_NEAR_LAUNCH(false, true, 2); else SL_NEAR_LAUNCH(false, false, 0);
+    }
+#undef SL_NEAR_LAUNCH
     if (tm && tm->e2) (void)hipEventRecord(tm->e2, st);
     return hipGetLastError();
 }

@@ -67,6 +67,7 @@ struct ReqDesc {
     double delta, scale;
     uint64_t gather_target, items_target, seq;
     int64_t mixed;
+    double rho64;                         // mixed: double-precision zone p < rho64
 };
 
 struct ServeCtl {                         // host-pinned
@@ -82,7 +83,8 @@ struct DevCounters {                      // device memory
     uint64_t tail_mirror;                 // latest host tail seen by any wave
     uint64_t stop_mirror;                 // host stop flag seen by any wave
     uint64_t last_poll;                   // wall clock of the latest read of host memory
-    uint64_t pad[3];
+    uint64_t launch_seen;                 // id of the launch that last reset last_activity
+    uint64_t pad[2];
     uint64_t gathers_done[kMaxSlots];     // monotonic per slot
     uint64_t items_done[kMaxSlots];       // monotonic per slot
 };
@@ -96,6 +98,7 @@ struct ServeArgs {
     uint64_t idle_ticks;                  // exit after this long without a claim
     uint64_t wait_ticks;                  // longest wait of a pair item for its gathers
     uint64_t poll_ticks;                  // spacing of the host-memory polls
+    uint64_t launch_id;                   // distinct for every launch
 };
 
 // ------------------------------------------------------------------------------------------
@@ -215,6 +218,7 @@ __device__ void run_pair(const ServeArgs &a, const WorkItem &it)
     const TBlockRec rec = tbr[it.a];
     const double gap_far = mixed ? rec.gap_far_mixed : rec.gap_far;
     const DeltaC dc = make_delta(delta);
+    const DeltaC32 dc32 = make_delta32(delta, field(&d->rho64));
     double tx[R], ty[R], tz[R], ax[R], ay[R], az[R];
     float tx32[R], ty32[R], tz32[R], hx[R], hy[R], hz[R], lx[R], ly[R], lz[R];
 #pragma unroll
@@ -264,6 +268,30 @@ __device__ void run_pair(const ServeArgs &a, const WorkItem &it)
                     for (int r = 0; r < R; ++r)
                         far_pair64(tx[r], ty[r], tz[r], s0, s1, s2, g0, g1, g2, ax[r], ay[r], az[r]);
                 }
+            } else if (mixed) {
+                const float qx = sx32[j0 + lane], qy = sy32[j0 + lane], qz = sz32[j0 + lane];
+                const float ex = gx32[j0 + lane], ey = gy32[j0 + lane], ez = gz32[j0 + lane];
+                float px[R], py[R], pz[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
+#pragma unroll 1
+                for (int j = 0; j < kCluster; ++j) {
+                    const double s0 = bcast(vx, j), s1 = bcast(vy, j), s2 = bcast(vz, j);
+                    const double g0 = bcast(wx, j), g1 = bcast(wy, j), g2 = bcast(wz, j);
+                    const float f0 = bcast(qx, j), f1 = bcast(qy, j), f2 = bcast(qz, j);
+                    const float h0 = bcast(ex, j), h1 = bcast(ey, j), h2 = bcast(ez, j);
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        near_pair_mixed(tx32[r], ty32[r], tz32[r], tx[r], ty[r], tz[r], f0, f1, f2,
+                                        h0, h1, h2, s0, s1, s2, g0, g1, g2, dc, dc32, px[r], py[r],
+                                        pz[r], ax[r], ay[r], az[r]);
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    two_sum_acc(px[r], hx[r], lx[r]);
+                    two_sum_acc(py[r], hy[r], ly[r]);
+                    two_sum_acc(pz[r], hz[r], lz[r]);
+                }
             } else {
 #pragma unroll 1
                 for (int j = 0; j < kCluster; ++j) {
@@ -303,9 +331,16 @@ __device__ void run_pair(const ServeArgs &a, const WorkItem &it)
 __global__ __launch_bounds__(kWave) void k_serve(ServeArgs a)
 {
     const int lane = threadIdx.x;
-    if (lane == 0)
-        __hip_atomic_fetch_max(&a.dc->last_activity, (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0) {
+        // The first wave of this launch starts the idle clock; later-starting waves must not
+        // push it forward, or the kernel would outlive its idle limit.
+        uint64_t seen = __hip_atomic_load(&a.dc->launch_seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (seen != a.launch_id &&
+            __hip_atomic_compare_exchange_strong(&a.dc->launch_seen, &seen, a.launch_id, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            __hip_atomic_fetch_max(&a.dc->last_activity, (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
     int rounds = 0;
     for (;;) {
         uint64_t idx = 0, got = 0, quit = 0;
@@ -435,7 +470,8 @@ __global__ __launch_bounds__(kWave) void k_tblock_serve(const double *__restrict
         rec.cx = cx; rec.cy = cy; rec.cz = cz;
         rec.rad = sqrt(rr) * (1.0 + 0x1p-40);
         rec.gap_far = kRhoExact64 * delta;
-        rec.gap_far_mixed = fmax(rho64 * delta, 0x1p-10 * sqrt(fma(bx, bx, fma(by, by, __dmul_rn(bz, bz)))));
+        rec.gap_far_mixed = fmax(fmax(kRhoExact32, rho64) * delta,
+                                 0x1p-10 * sqrt(fma(bx, bx, fma(by, by, __dmul_rn(bz, bz)))));
         rec.pad0 = rec.pad1 = 0.0;
         out[tb] = rec;
     }
@@ -524,6 +560,7 @@ struct HostReq {
     const double *fx, *fy, *fz;
     double *ux, *uy, *uz;
     double mu = 1.0;
+    double rho64 = 1.0;
     ReqState state = ReqState::Pending;
     int slot = -1;
     char *staging = nullptr;
@@ -721,6 +758,7 @@ void Server::admit_locked()
         d.items_target = items_cum[slot];
         d.seq = r.seq;
         d.mixed = r.mixed ? 1 : 0;
+        d.rho64 = r.rho64;
         memcpy((void *)&desc[slot], &d, sizeof(d));
         for (uint64_t k = 0; k < n_gather; ++k) {
             const int64_t a = (int64_t)k * kGatherChunk;
@@ -749,8 +787,15 @@ sl_status Server::ensure_kernel_locked()
     }
     ServeArgs a{ctl, ring, desc, done_seq, dc,
                 (uint64_t)(kIdleSeconds * clock_hz), (uint64_t)(kGatherWaitSeconds * clock_hz),
-                (uint64_t)(kPollSeconds * clock_hz) + 1};
-    const unsigned grid = (unsigned)(ctx->n_cu * 4 * kServeWavesPerSimd);
+                (uint64_t)(kPollSeconds * clock_hz) + 1, stats.kernel_launches + 1};
+    // All waves resident at once (so that they share one idle clock), at most kServeWavesPerSimd
+    // per SIMD.
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_serve, kWave, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 4;
+    per_cu = per_cu < 4 * kServeWavesPerSimd ? per_cu : 4 * kServeWavesPerSimd;
+    const unsigned grid = (unsigned)(ctx->n_cu * per_cu);
     hipLaunchKernelGGL(k_serve, dim3(grid), dim3(kWave), 0, kstream, a);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipEventRecord(kdone, kstream);
@@ -958,6 +1003,7 @@ sl_status sl_submit(sl_ctx *ctx, uint64_t handle, sl_precision prec, const doubl
     r.fx = fx; r.fy = fy; r.fz = fz;
     r.ux = ux; r.uy = uy; r.uz = uz;
     r.mu = mu;
+    r.rho64 = ctx->rho64;
     sf.refs += 1;
     s->reqs[r.id] = r;
     s->pending.push_back(r.id);

@@ -77,8 +77,9 @@ def measure_precision(ctx, P, prob, tens, precision, steps, warmup):
     t = time_steps(fn, steps, 0)
     P.check(P.sl_set_param(ctx.ptr, P.SL_PARAM_KERNEL_TIMING, 0.0))
     s1 = P.sl_get_stats(ctx.ptr)
-    launches = s1.pair_launches - s0.pair_launches
-    kern_ms = (s1.pair_ms - s0.pair_ms) / max(1, launches)
+    launches = max(1, s1.pair_launches - s0.pair_launches)
+    kern_ms = (s1.pair_ms - s0.pair_ms) / launches
+    measure_precision.split = ((s1.far_ms - s0.far_ms) / launches, (s1.near_ms - s0.near_ms) / launches)
     return t * 1e3, kern_ms, out
 
 
@@ -100,16 +101,123 @@ def roofline(precision, pairs, near, kern_ms):
 
 
 def cpu_baseline(prob):
-    """The oracle as it stands, on the host cores, over the whole workload (all targets)."""
+    """The oracle as it stands, on the host cores, over the whole workload (all targets).
+    Returns the baseline record and the oracle's result (the reference for eps)."""
     import oracle
     oracle.build(force=False)
     threads = oracle.max_threads()
     t0 = time.perf_counter()
-    oracle.single_layer(prob.surface.X, prob.surface.w, prob.f, prob.delta)
+    ref = oracle.single_layer(prob.surface.X, prob.surface.w, prob.f, prob.delta)
     dt = time.perf_counter() - t0
-    return {"value": round(prob.N ** 2 / dt / 1e9, 4), "unit": "Gpair/s", "cores": threads,
-            "kind": "oracle", "seconds": round(dt, 3),
-            "sample": f"all {prob.N} targets x {prob.N} sources of the same surface and density"}
+    return ({"value": round(prob.N ** 2 / dt / 1e9, 4), "unit": "Gpair/s", "cores": threads,
+             "kind": "oracle", "seconds": round(dt, 3),
+             "sample": f"all {prob.N} targets x {prob.N} sources of the same surface and density"},
+            ref)
+
+
+def rel_inf(u, ref):
+    import numpy as np
+    return float(np.max(np.abs(u - ref)) / np.max(np.abs(ref)))
+
+
+def pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
+
+
+def run_stream(ctx, P, handles, fs, us, pairs, arrivals, precision, spin):
+    """Submit request k at arrivals[k] seconds after the start; poll until all are done.
+    Returns (makespan s, latencies s = completion - scheduled arrival)."""
+    n = len(handles)
+    done_at = [None] * n
+    rid_of = {}
+    t0 = time.perf_counter()
+    k = 0
+    outstanding = []
+    while k < n or outstanding:
+        now = time.perf_counter() - t0
+        while k < n and arrivals[k] <= now:
+            rid = ctx.submit_prepared(handles[k], fs[k], us[k], precision=precision)
+            rid_of[rid] = k
+            outstanding.append(rid)
+            k += 1
+        still = []
+        for rid in outstanding:
+            st, done = P.sl_poll(ctx.ptr, rid)
+            P.check(st, "sl_poll")
+            if done:
+                done_at[rid_of[rid]] = time.perf_counter() - t0
+            else:
+                still.append(rid)
+        outstanding = still
+        if spin:
+            time.sleep(spin)
+    makespan = max(done_at)
+    return makespan, [done_at[i] - arrivals[i] for i in range(n)]
+
+
+def serving_leg(P, dev, log):
+    """The request stream: 256 capsules (sphere / ellipsoid 1:0.8:0.5 / RBC, n log-uniform in
+    [16, 192]), surfaces registered (resident) first; then a burst at t = 0 (capacity) and
+    Poisson arrivals at 70% of the measured capacity, in mixed and in FP64, plus the same
+    requests evaluated one at a time with sl_eval in FP64."""
+    import numpy as np
+    import torch
+    from capsule_inputs import workloads as W
+    t_gen = time.perf_counter()
+    stream = W.serving_stream()
+    probs = [r.problem() for r in stream.requests]
+    log(f"[bench] serving stream: {len(probs)} requests generated in "
+        f"{time.perf_counter() - t_gen:.1f} s")
+    pairs = [p.N * p.N for p in probs]
+    total = float(sum(pairs))
+    out = {"workload": "256 requests: sphere / ellipsoid 1:0.8:0.5 / RBC, N = 6 n^2, n "
+                       "log-uniform in [16, 192], SH density, delta = 2h",
+           "total_pairs": total, "requests": len(probs)}
+    with P.Context(0, hbm_budget_bytes=8 << 30) as ctx:
+        t = lambda a: torch.as_tensor(a, device=dev)
+        handles = [ctx.register_surface(t(p.surface.X), t(p.surface.w), p.delta) for p in probs]
+        fs = [t(np.ascontiguousarray(p.f.T)) for p in probs]
+        us = [torch.empty_like(f) for f in fs]
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(W.SEED_C4 + 1)
+        mean_pairs = total / len(probs)
+        for prec in ("mixed", "fp64"):
+            run_stream(ctx, P, handles[:8], fs[:8], us[:8], pairs[:8], [0.0] * 8, prec, 0)  # warm
+            mk, lat = run_stream(ctx, P, handles, fs, us, pairs, [0.0] * len(probs), prec, 0)
+            cap_rps = len(probs) / mk
+            rate = 0.7 * cap_rps
+            gaps = rng.exponential(1.0 / rate, size=len(probs))
+            arrivals = list(np.cumsum(gaps) - gaps[0])
+            mk2, lat2 = run_stream(ctx, P, handles, fs, us, pairs, arrivals, prec, 0)
+            out[prec] = {
+                "burst": {"makespan_s": round(mk, 4), "gpair_s": round(total / mk / 1e9, 2),
+                          "p50_ms": round(pct(lat, 50) * 1e3, 3), "p99_ms": round(pct(lat, 99) * 1e3, 3)},
+                "poisson": {"rate_hz": round(rate, 2), "offered_load": 0.7,
+                            "makespan_s": round(mk2, 4),
+                            "gpair_s": round(total / mk2 / 1e9, 2),
+                            "p50_ms": round(pct(lat2, 50) * 1e3, 3),
+                            "p99_ms": round(pct(lat2, 99) * 1e3, 3),
+                            "max_ms": round(max(lat2) * 1e3, 3)}}
+            log(f"[bench] serving {prec}: burst {total / mk / 1e9:.0f} Gpair/s; Poisson at "
+                f"{rate:.0f}/s: p50 {pct(lat2, 50) * 1e3:.2f} ms p99 {pct(lat2, 99) * 1e3:.2f} ms")
+        st = ctx.stats()
+        out["kernel_launches"] = int(st.kernel_launches)
+        out["requests_done"] = int(st.requests_done)
+        # one at a time, FP64, sl_eval on the same GPU
+        ev = P.Context(0)
+        Xs = [t(p.surface.X) for p in probs]
+        ws = [t(p.surface.w) for p in probs]
+        Fs = [t(p.f) for p in probs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for p, X, w, F in zip(probs, Xs, ws, Fs):
+            ev.single_layer(X, w, F, p.delta, precision="fp64")
+            torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ev.close()
+        out["fp64_one_at_a_time"] = {"seconds": round(dt, 4), "gpair_s": round(total / dt / 1e9, 2)}
+    return out
 
 
 def main():
@@ -120,6 +228,7 @@ def main():
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the large-N and serving legs")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one device copy of this many bytes (PMC calibration)")
     args = ap.parse_args()
@@ -144,11 +253,14 @@ def main():
     near = count_near(tens[0], prob.delta, [RHO_EXACT64, 5.0])
 
     res = {}
+    outs = {}
     for prec in ("fp64", "mixed"):
-        ms, kern_ms, _ = measure_precision(ctx, P, prob, tens, prec, args.steps, args.warmup)
+        ms, kern_ms, outs[prec] = measure_precision(ctx, P, prob, tens, prec, args.steps, args.warmup)
         near_p = near[RHO_EXACT64] if prec == "fp64" else near[5.0]
         res[prec] = {"ms_per_step": round(ms, 4), "gpair_s": round(pairs / (ms * 1e-3) / 1e9, 3),
                      "roofline": roofline(prec, pairs, near_p, kern_ms)}
+        res[prec]["roofline"]["far_kernel_ms"] = round(measure_precision.split[0], 4)
+        res[prec]["roofline"]["near_kernel_ms"] = round(measure_precision.split[1], 4)
         log(f"[bench] {prec}: {ms:.3f} ms/step  {res[prec]['gpair_s']:.1f} Gpair/s  "
             f"pair kernel {kern_ms:.3f} ms  {res[prec]['roofline']['frac'] * 100:.1f}% of peak")
 
@@ -170,18 +282,36 @@ def main():
         other: res[other],
     }
 
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline: oracle on the host")
+        line["cpu_baseline"], ref = cpu_baseline(prob)
+        for prec in ("fp64", "mixed"):
+            e = rel_inf(outs[prec].t().cpu().numpy(), ref)
+            (line if prec == args.precision else line[prec])["eps_vs_oracle"] = e
+            log(f"[bench] {prec}: eps vs oracle {e:.2e}")
+
     if not args.no_extras:
+        import oracle
         p3 = W.c3()
         t3 = tuple(torch.as_tensor(a, device=dev) for a in (p3.surface.X, p3.surface.w, p3.f))
         big = {"workload": "rbc_6x256x256_sh8", "N": p3.N}
+        idx = W.c3_subset(p3.N, 256)
+        ref3 = oracle.single_layer(p3.surface.X, p3.surface.w, p3.f, p3.delta,
+                                   targets=p3.surface.X[idx])
         for prec in ("fp64", "mixed"):
-            ms, kern_ms, _ = measure_precision(ctx, P, p3, t3, prec, 3, 1)
+            ms, kern_ms, u3 = measure_precision(ctx, P, p3, t3, prec, 3, 1)
             big[prec] = {"ms_per_step": round(ms, 3),
                          "gpair_s": round(p3.N ** 2 / (ms * 1e-3) / 1e9, 2),
-                         "pair_kernel_ms": round(kern_ms, 3)}
-            log(f"[bench] N={p3.N} {prec}: {ms:.2f} ms  {big[prec]['gpair_s']:.0f} Gpair/s")
+                         "pair_kernels_ms": round(kern_ms, 3),
+                         "eps_vs_oracle_256_targets": rel_inf(u3.t().cpu().numpy()[idx], ref3)}
+            log(f"[bench] N={p3.N} {prec}: {ms:.2f} ms  {big[prec]['gpair_s']:.0f} Gpair/s  "
+                f"eps {big[prec]['eps_vs_oracle_256_targets']:.2e}")
         line["large_n"] = big
         del t3
+        if not args.no_serving:
+            line["serving"] = serving_leg(P, dev, log)
+            line["p50_ms"] = line["serving"]["mixed"]["poisson"]["p50_ms"]
+            line["p99_ms"] = line["serving"]["mixed"]["poisson"]["p99_ms"]
 
     if args.copy_bytes:
         a = torch.empty(args.copy_bytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
@@ -191,9 +321,6 @@ def main():
         torch.cuda.synchronize()
         line["copy_calibration_bytes"] = args.copy_bytes
 
-    if not args.no_cpu_baseline:
-        log("[bench] cpu baseline: oracle on the host")
-        line["cpu_baseline"] = cpu_baseline(prob)
     ctx.close()
     print(json.dumps(line), flush=True)
 

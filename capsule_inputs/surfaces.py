@@ -178,10 +178,14 @@ def make_surface(shape: Shape, n: int) -> Surface:
         nrm = cr / W
         # Orientation: the charts are right-handed w.r.t. the outward sphere
         # normal and every phi used here has det(D phi) > 0, so x_u x x_v points
-        # outward. Checked rather than assumed:
-        Jinv_T = np.linalg.inv(np.moveaxis(J, (0, 1), (-2, -1))).swapaxes(-1, -2)
-        push = np.einsum("...ab,b...->a...", Jinv_T, p)
-        if np.any(np.einsum("a...,a...->...", nrm, push) <= 0):
+        # outward. Checked rather than assumed: the pushed-forward sphere normal is
+        # det(J) J^{-T} x0 = ((J2 x J3).x0, (J3 x J1).x0, (J1 x J2).x0), J_k the rows of J.
+        r1, r2, r3 = J[0], J[1], J[2]
+        push = np.array([np.einsum("a...,a...->...", np.cross(r2, r3, axis=0), p),
+                         np.einsum("a...,a...->...", np.cross(r3, r1, axis=0), p),
+                         np.einsum("a...,a...->...", np.cross(r1, r2, axis=0), p)])
+        det = np.einsum("a...,a...->...", r1, np.cross(r2, r3, axis=0))
+        if np.any(det <= 0) or np.any(np.einsum("a...,a...->...", nrm, push) <= 0):
             raise RuntimeError("chart orientation is not outward")
         psi = pou(p)[i - 1]
         Xs.append(X.reshape(3, -1).T)

@@ -114,6 +114,15 @@ class Context:
         self._inflight[rid] = (fs, U)
         return rid, U
 
+    def submit_prepared(self, handle: int, fs, U, mu=1.0, precision="mixed") -> int:
+        """sl_submit on ready (3, N) float64 device tensors (no copy, no synchronization);
+        the caller keeps fs and U alive until the request is done."""
+        st, rid = sl_submit(self.ptr, handle, PRECISIONS[precision], fs[0].data_ptr(),
+                            fs[1].data_ptr(), fs[2].data_ptr(), float(mu), U[0].data_ptr(),
+                            U[1].data_ptr(), U[2].data_ptr())
+        check(st, "sl_submit")
+        return rid
+
     def wait(self, rid: int, timeout_s: float = 60.0):
         check(sl_wait(self.ptr, rid, timeout_s), "sl_wait")
         return self._inflight.pop(rid)[1].t()

@@ -143,6 +143,20 @@ def test_real_harmonics_are_orthonormal():
     assert np.allclose(G, np.eye(len(lm)), atol=1e-6)
 
 
+def test_batched_harmonics_match_scipy_legendre():
+    """The recurrence used for the force densities equals the scipy lpmv-based definition,
+    including at the poles."""
+    from capsule_inputs.forces import real_sph_harm_all
+    s = make_surface(SPHERE, 9)
+    x0 = np.concatenate([s.x0, [[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]]])
+    Y = real_sph_harm_all(x0, 8)
+    k = 0
+    for l in range(9):
+        for m in range(-l, l + 1):
+            assert np.allclose(Y[:, k], real_sph_harm(l, m, x0), atol=1e-12, rtol=1e-12)
+            k += 1
+
+
 def test_sh_force_is_seeded():
     s = make_surface(RBC, 8)
     assert np.array_equal(sh_force(s.x0, 7), sh_force(s.x0, 7))

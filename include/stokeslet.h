@@ -75,10 +75,11 @@ const char *sl_last_error(void);
  *   sl_submit.
  * SL_PARAM_KERNEL_TIMING: 1 = bracket every pair-kernel launch of sl_eval with HIP events on
  *   the caller's stream and accumulate the elapsed time into sl_stats; 0 (default) = off.
- * SL_PARAM_TARGETS_PER_LANE: targets each lane of the pair kernel keeps in registers
- *   (1, 2 or 4; default 2).
- * SL_PARAM_WAVES_PER_SIMD: the pair kernel splits the sources until the launch holds about
- *   this many wavefronts per SIMD (1..32; default 4). */
+ * SL_PARAM_TARGETS_PER_LANE: targets each lane of the pair kernels keeps in registers
+ *   (1, 2 or 4; 0 = automatic, the default: 1 in SL_MIXED, 2 in SL_FP64, 4 in SL_FP64 from
+ *   2^17 targets).
+ * SL_PARAM_WAVES_PER_SIMD: granularity of the pair kernels' work items: the sources are split
+ *   until there are about this many items per SIMD (1..32; default 16). */
 typedef enum {
     SL_PARAM_RHO64 = 0,
     SL_PARAM_KERNEL_TIMING = 1,

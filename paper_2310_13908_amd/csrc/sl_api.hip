@@ -144,8 +144,8 @@ sl_status sl_set_param(sl_ctx *ctx, sl_param key, double value)
         return SL_OK;
     }
     if (key == SL_PARAM_TARGETS_PER_LANE) {
-        if (value != 1.0 && value != 2.0 && value != 4.0)
-            return fail(SL_EINVAL, "sl_set_param: targets per lane is 1, 2 or 4");
+        if (value != 0.0 && value != 1.0 && value != 2.0 && value != 4.0)
+            return fail(SL_EINVAL, "sl_set_param: targets per lane is 0 (automatic), 1, 2 or 4");
         std::lock_guard<std::mutex> l(ctx->mu);
         ctx->targets_per_lane = (int)value;
         return SL_OK;
@@ -267,6 +267,8 @@ sl_status sl_eval(sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *s
         R = ctx->targets_per_lane;
         wps = ctx->waves_per_simd;
     }
+    if (R == 0)   // measured on MI355X: the single-precision loops want occupancy, FP64 ILP
+        R = mixed ? 1 : (np_t >= ((int64_t)1 << 17) ? 4 : 2);
     PairPlan plan = plan_pairs(np_s, np_t, R, ctx->n_cu * 4 * wps);
     plan.n_cu = ctx->n_cu;
 

@@ -167,8 +167,8 @@ struct sl_ctx {
     int n_cu = 0;
     size_t budget = 0;
     double rho64 = 1.0;
-    int targets_per_lane = 2;
-    int waves_per_simd = 4;
+    int targets_per_lane = 0;   // 0: chosen per call
+    int waves_per_simd = 16;
     std::mutex mu;
     sl::Server *server = nullptr;
     // pair-kernel timing (SL_PARAM_KERNEL_TIMING)

@@ -271,7 +271,7 @@ __device__ __forceinline__ void near_item(const PairArgs &a, const TBlockRec *__
                 float px[R], py[R], pz[R];
 #pragma unroll
                 for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
-#pragma unroll 1
+#pragma unroll 4
                 for (int j = 0; j < kCluster; ++j) {
                     const float sx32 = Sx32[j0 + j], sy32 = Sy32[j0 + j], sz32 = Sz32[j0 + j];
                     const float gx32 = Gx32[j0 + j], gy32 = Gy32[j0 + j], gz32 = Gz32[j0 + j];
@@ -291,7 +291,7 @@ __device__ __forceinline__ void near_item(const PairArgs &a, const TBlockRec *__
                     two_sum_acc(pz[r], hz[r], lz[r]);
                 }
             } else {
-#pragma unroll 1
+#pragma unroll 2
                 for (int j = 0; j < kCluster; ++j) {
                     const double sx = Sx[j0 + j], sy = Sy[j0 + j], sz = Sz[j0 + j];
                     const double gx = Gx[j0 + j], gy = Gy[j0 + j], gz = Gz[j0 + j];

@@ -79,7 +79,6 @@ def measure_precision(ctx, P, prob, tens, precision, steps, warmup):
     s1 = P.sl_get_stats(ctx.ptr)
     launches = max(1, s1.pair_launches - s0.pair_launches)
     kern_ms = (s1.pair_ms - s0.pair_ms) / launches
-    measure_precision.split = ((s1.far_ms - s0.far_ms) / launches, (s1.near_ms - s0.near_ms) / launches)
     return t * 1e3, kern_ms, out
 
 
@@ -156,11 +155,12 @@ def run_stream(ctx, P, handles, fs, us, pairs, arrivals, precision, spin):
     return makespan, [done_at[i] - arrivals[i] for i in range(n)]
 
 
-def serving_leg(P, dev, log):
+def serving_leg(P, dev, log, check_oracle=True):
     """The request stream: 256 capsules (sphere / ellipsoid 1:0.8:0.5 / RBC, n log-uniform in
     [16, 192]), surfaces registered (resident) first; then a burst at t = 0 (capacity) and
-    Poisson arrivals at 70% of the measured capacity, in mixed and in FP64, plus the same
-    requests evaluated one at a time with sl_eval in FP64."""
+    Poisson arrivals at 50% and 90% of the measured capacity, in mixed and in FP64, plus the
+    same requests evaluated one at a time with sl_eval in FP64.  Every burst result is checked
+    against the oracle on up to 256 sampled targets per request."""
     import numpy as np
     import torch
     from capsule_inputs import workloads as W
@@ -174,6 +174,17 @@ def serving_leg(P, dev, log):
     out = {"workload": "256 requests: sphere / ellipsoid 1:0.8:0.5 / RBC, N = 6 n^2, n "
                        "log-uniform in [16, 192], SH density, delta = 2h",
            "total_pairs": total, "requests": len(probs)}
+    refs = None
+    if check_oracle:
+        import oracle
+        rng_t = np.random.default_rng(W.SEED_C4 + 2)
+        t0 = time.perf_counter()
+        refs = []
+        for p in probs:
+            idx = np.sort(rng_t.choice(p.N, size=min(256, p.N), replace=False))
+            refs.append((idx, oracle.single_layer(p.surface.X, p.surface.w, p.f, p.delta,
+                                                  targets=p.surface.X[idx])))
+        log(f"[bench] serving: oracle on sampled targets in {time.perf_counter() - t0:.1f} s")
     with P.Context(0, hbm_budget_bytes=8 << 30) as ctx:
         t = lambda a: torch.as_tensor(a, device=dev)
         handles = [ctx.register_surface(t(p.surface.X), t(p.surface.w), p.delta) for p in probs]
@@ -181,26 +192,31 @@ def serving_leg(P, dev, log):
         us = [torch.empty_like(f) for f in fs]
         torch.cuda.synchronize()
         rng = np.random.default_rng(W.SEED_C4 + 1)
-        mean_pairs = total / len(probs)
         for prec in ("mixed", "fp64"):
             run_stream(ctx, P, handles[:8], fs[:8], us[:8], pairs[:8], [0.0] * 8, prec, 0)  # warm
             mk, lat = run_stream(ctx, P, handles, fs, us, pairs, [0.0] * len(probs), prec, 0)
+            rec = {"burst": {"makespan_s": round(mk, 4), "gpair_s": round(total / mk / 1e9, 2),
+                             "p50_ms": round(pct(lat, 50) * 1e3, 3),
+                             "p99_ms": round(pct(lat, 99) * 1e3, 3)}}
+            if refs is not None:
+                eps = [rel_inf(u.t().cpu().numpy()[idx], ref) for u, (idx, ref) in zip(us, refs)]
+                rec["burst"]["max_eps_vs_oracle"] = max(eps)
             cap_rps = len(probs) / mk
-            rate = 0.7 * cap_rps
-            gaps = rng.exponential(1.0 / rate, size=len(probs))
-            arrivals = list(np.cumsum(gaps) - gaps[0])
-            mk2, lat2 = run_stream(ctx, P, handles, fs, us, pairs, arrivals, prec, 0)
-            out[prec] = {
-                "burst": {"makespan_s": round(mk, 4), "gpair_s": round(total / mk / 1e9, 2),
-                          "p50_ms": round(pct(lat, 50) * 1e3, 3), "p99_ms": round(pct(lat, 99) * 1e3, 3)},
-                "poisson": {"rate_hz": round(rate, 2), "offered_load": 0.7,
-                            "makespan_s": round(mk2, 4),
-                            "gpair_s": round(total / mk2 / 1e9, 2),
-                            "p50_ms": round(pct(lat2, 50) * 1e3, 3),
-                            "p99_ms": round(pct(lat2, 99) * 1e3, 3),
-                            "max_ms": round(max(lat2) * 1e3, 3)}}
-            log(f"[bench] serving {prec}: burst {total / mk / 1e9:.0f} Gpair/s; Poisson at "
-                f"{rate:.0f}/s: p50 {pct(lat2, 50) * 1e3:.2f} ms p99 {pct(lat2, 99) * 1e3:.2f} ms")
+            for load in (0.5, 0.9):
+                rate = load * cap_rps
+                gaps = rng.exponential(1.0 / rate, size=len(probs))
+                arrivals = list(np.cumsum(gaps) - gaps[0])
+                mk2, lat2 = run_stream(ctx, P, handles, fs, us, pairs, arrivals, prec, 0)
+                rec[f"poisson_{load}"] = {
+                    "rate_hz": round(rate, 2), "offered_load": load,
+                    "makespan_s": round(mk2, 4), "gpair_s": round(total / mk2 / 1e9, 2),
+                    "p50_ms": round(pct(lat2, 50) * 1e3, 3), "p99_ms": round(pct(lat2, 99) * 1e3, 3),
+                    "max_ms": round(max(lat2) * 1e3, 3)}
+                log(f"[bench] serving {prec}: Poisson at {rate:.0f}/s (load {load}): "
+                    f"p50 {pct(lat2, 50) * 1e3:.2f} ms p99 {pct(lat2, 99) * 1e3:.2f} ms")
+            out[prec] = rec
+            log(f"[bench] serving {prec}: burst {total / mk / 1e9:.0f} Gpair/s"
+                + (f", max eps {rec['burst']['max_eps_vs_oracle']:.2e}" if refs is not None else ""))
         st = ctx.stats()
         out["kernel_launches"] = int(st.kernel_launches)
         out["requests_done"] = int(st.requests_done)
@@ -220,6 +236,72 @@ def serving_leg(P, dev, log):
     return out
 
 
+def memory_leg(P, dev, log, n_large=4, n_small=124):
+    """A scaled sample of the memory-admitted stream: n_large capsules of N = 6 * 512^2
+    interleaved with n_small ones (n log-uniform in [16, 64]), RBC and ellipsoid.  The client
+    registers each surface as its request arrives, submits, and releases surfaces once their
+    request is done; when registration is refused for lack of memory it first retires the
+    oldest request.  Run with the full budget and with one of about two large surfaces."""
+    import collections
+    import numpy as np
+    import torch
+    from capsule_inputs import workloads as W
+    stream = W.memory_admitted_stream(n_large=n_large, n_small=n_small)
+    t0 = time.perf_counter()
+    probs = [r.problem() for r in stream.requests]
+    log(f"[bench] memory stream: {len(probs)} requests generated in {time.perf_counter() - t0:.1f} s")
+    total = float(sum(p.N * p.N for p in probs))
+    n_big = max(p.N for p in probs)
+    per_point = 85                       # resident surface (49 B) + mixed staging (36 B) per point
+    budgets = {"full": 16 << 30, "two_large": int(2.5 * per_point * n_big)}
+    out = {"workload": f"{n_large} capsules N = {n_big} + {n_small} with n in [16, 64] "
+                       "(RBC / ellipsoid), SH density, delta = 2h; surfaces registered on "
+                       "arrival and released after their request",
+           "total_pairs": total, "requests": len(probs)}
+    for bname, budget in budgets.items():
+        for prec in ("mixed", "fp64"):
+            with P.Context(0, hbm_budget_bytes=budget) as ctx:
+                torch.cuda.synchronize()
+                live = collections.deque()
+                refused = 0
+                peak = 0
+                t0 = time.perf_counter()
+                for p in probs:
+                    X = torch.as_tensor(p.surface.X, device=dev)
+                    w = torch.as_tensor(p.surface.w, device=dev)
+                    f = torch.as_tensor(np.ascontiguousarray(p.f.T), device=dev)
+                    u = torch.empty_like(f)
+                    torch.cuda.synchronize()
+                    while True:
+                        try:
+                            h = ctx.register_surface(X, w, p.delta)
+                            break
+                        except P.SlError as e:
+                            if e.status != P.SL_EBUSY or not live:
+                                raise
+                            refused += 1
+                            rid0, h0, _ = live.popleft()
+                            ctx.wait(rid0, 600.0)
+                            ctx.release_surface(h0)
+                    rid = ctx.submit_prepared(h, f, u, precision=prec)
+                    live.append((rid, h, (f, u)))
+                    peak = max(peak, int(ctx.stats().bytes_admitted))
+                    while live and ctx.poll(live[0][0]):
+                        ctx.release_surface(live.popleft()[1])
+                while live:
+                    rid0, h0, _ = live.popleft()
+                    ctx.wait(rid0, 600.0)
+                    ctx.release_surface(h0)
+                dt = time.perf_counter() - t0
+            out[f"{bname}_{prec}"] = {"budget_bytes": budget, "seconds": round(dt, 3),
+                                      "gpair_s": round(total / dt / 1e9, 2),
+                                      "registrations_refused": refused,
+                                      "peak_bytes_admitted": peak}
+            log(f"[bench] memory stream {bname} {prec}: {dt:.2f} s  {total / dt / 1e9:.0f} Gpair/s  "
+                f"refused {refused}  peak {peak / 2**30:.2f} GiB")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,6 +311,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the large-N and serving legs")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-memory-stream", action="store_true",
+                    help="skip the memory-admitted stream leg")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one device copy of this many bytes (PMC calibration)")
     args = ap.parse_args()
@@ -259,8 +343,6 @@ def main():
         near_p = near[RHO_EXACT64] if prec == "fp64" else near[5.0]
         res[prec] = {"ms_per_step": round(ms, 4), "gpair_s": round(pairs / (ms * 1e-3) / 1e9, 3),
                      "roofline": roofline(prec, pairs, near_p, kern_ms)}
-        res[prec]["roofline"]["far_kernel_ms"] = round(measure_precision.split[0], 4)
-        res[prec]["roofline"]["near_kernel_ms"] = round(measure_precision.split[1], 4)
         log(f"[bench] {prec}: {ms:.3f} ms/step  {res[prec]['gpair_s']:.1f} Gpair/s  "
             f"pair kernel {kern_ms:.3f} ms  {res[prec]['roofline']['frac'] * 100:.1f}% of peak")
 
@@ -310,8 +392,10 @@ def main():
         del t3
         if not args.no_serving:
             line["serving"] = serving_leg(P, dev, log)
-            line["p50_ms"] = line["serving"]["mixed"]["poisson"]["p50_ms"]
-            line["p99_ms"] = line["serving"]["mixed"]["poisson"]["p99_ms"]
+            line["p50_ms"] = line["serving"]["mixed"]["poisson_0.9"]["p50_ms"]
+            line["p99_ms"] = line["serving"]["mixed"]["poisson_0.9"]["p99_ms"]
+        if not args.no_memory_stream:
+            line["memory_stream"] = memory_leg(P, dev, log)
 
     if args.copy_bytes:
         a = torch.empty(args.copy_bytes // 8, dtype=torch.float64, device=dev).fill_(1.0)

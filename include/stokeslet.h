@@ -158,9 +158,7 @@ typedef struct {
     uint64_t kernel_launches;
     uint64_t bytes_admitted;
     uint64_t pair_launches;
-    double pair_ms;       /* far_ms + near_ms */
-    double far_ms;        /* kernel over source clusters classified far (plain Stokeslet) */
-    double near_ms;       /* kernel over clusters near the targets (regularized, FP64) */
+    double pair_ms;       /* summed duration of the timed pair-kernel launches */
 } sl_stats;
 sl_status sl_get_stats(sl_ctx *ctx, sl_stats *out);
 

@@ -124,14 +124,17 @@ class Context:
         return rid
 
     def wait(self, rid: int, timeout_s: float = 60.0):
+        """Block until request `rid` is done; returns its (N, 3) output if it was submitted with
+        submit(), else None."""
         check(sl_wait(self.ptr, rid, timeout_s), "sl_wait")
-        return self._inflight.pop(rid)[1].t()
+        entry = getattr(self, "_inflight", {}).pop(rid, None)
+        return entry[1].t() if entry else None
 
     def poll(self, rid: int) -> bool:
         st, done = sl_poll(self.ptr, rid)
         check(st, "sl_poll")
         if done:
-            self._inflight.pop(rid, None)
+            getattr(self, "_inflight", {}).pop(rid, None)
         return done
 
     def stats(self):

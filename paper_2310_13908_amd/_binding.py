@@ -36,8 +36,7 @@ class SlError(RuntimeError):
 class sl_stats(ctypes.Structure):
     _fields_ = [("requests_done", ctypes.c_uint64), ("items_done", ctypes.c_uint64),
                 ("kernel_launches", ctypes.c_uint64), ("bytes_admitted", ctypes.c_uint64),
-                ("pair_launches", ctypes.c_uint64), ("pair_ms", ctypes.c_double),
-                ("far_ms", ctypes.c_double), ("near_ms", ctypes.c_double)]
+                ("pair_launches", ctypes.c_uint64), ("pair_ms", ctypes.c_double)]
 
 
 _lib = None

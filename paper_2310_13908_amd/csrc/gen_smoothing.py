@@ -5,23 +5,25 @@ s2(p) = erf p - (2/3) p (4p^4 - 14p^2 + 3) e^{-p^2}/sqrt(pi)).
 
 The device code splits the regularized zone p = r/delta < 6.9 in two:
 
-* p^2 < 0.25: power series in q = p^2 of F1 = s1(p)/p and F2 = s2(p)/p^3, obtained by
-  expanding erf and exp term by term:
-      sqrt(pi) F1(q) = sum_n (-1)^n 8 (n+1)(n+2) q^n / (3 (2n+1) n!)
-      sqrt(pi) F2(q) = sum_n (-1)^n 16 (n+2)(n+3) q^n / (3 (2n+3) n!)
-  (F1(0) = 16/(3 sqrt(pi)), F2(0) = 32/(3 sqrt(pi)): the r -> 0 limits of Sec. 3.4).
-* 0.5 <= p < 6.9: s = 1 - e^{-q} (g(p) + P(p)) with the exact polynomial parts
+* q = p^2 < 1: F1 = s1(p)/p and F2 = s2(p)/p^3 as polynomials in x = q - 1/2, the interpolants
+  at Chebyshev nodes of [0, 1] of 40-digit values.  Both are entire functions of q with the
+  r -> 0 limits F1(0) = 16/(3 sqrt(pi)), F2(0) = 32/(3 sqrt(pi)) of Sec. 3.4, and the
+  polynomial has no cancellation near q = 0, where s2 itself loses all its digits.
+* 1 <= p < 6.9: s = 1 - e^{-q} (g(p) + P(p)) with the exact polynomial parts
   P1 = (2/3)p(2q-5)/sqrt(pi), P2 = (2/3)p(4q^2-14q+3)/sqrt(pi) and the scaled complementary
-  error function g(p) = e^{p^2} erfc(p), approximated by a polynomial in t = 3/(3+p)
-  interpolated at Chebyshev nodes with 40-digit mpmath values; e^{-q} uses its Taylor
-  series after reduction by powers of two.
+  error function g(p) = e^{p^2} erfc(p).  g enters s only through e^{-q} g, so its polynomial
+  (in t - t_mid, t = 3/(3+p)) is a least-squares fit weighted by e^{-q}: the weighted error
+  e^{-q} |g_fit - g| is what perturbs s.  e^{-q} = 2^-n e^{-f}, n = rint(q / ln 2),
+  |f| <= ln2/2, with e^x on |x| <= ln2/2 interpolated at Chebyshev nodes.
+
+The mixed-precision path evaluates the same formula in single precision on 0.5 <= p < 5 with
+a shorter fit of g (unweighted: single-precision rounding dominates there).
 
 Run: python gen_smoothing.py  (rewrites sl_smoothing_coeffs.h next to this file and prints the
 achieved double-precision error of every approximation).
 """
 from __future__ import annotations
 
-import math
 import os
 import struct
 
@@ -31,25 +33,41 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 OUT = os.path.join(HERE, "sl_smoothing_coeffs.h")
 
-SERIES_Q_MAX = 0.25     # series used for q = p^2 below this
-SERIES_TERMS = 14
-G_LO, G_HI = 0.5, 6.9   # range of the g fit (p)
+SERIES_Q_MAX = 1.0      # small-q polynomial used for q = p^2 below this
+SERIES_MID = 0.5        # ... in x = q - SERIES_MID
+SERIES_DEG = 12
+G_LO, G_HI = 1.0, 6.9   # range of the g fit (p)
 G_K = 3.0               # t = G_K / (G_K + p)
-G_DEG = 16
-EXP_DEG = 13            # Taylor degree of e^x on |x| <= ln2/2
+G_DEG = 11
+EXP_DEG = 11            # degree of e^x on |x| <= ln2/2
 # Single-precision smoothing of the mixed path (0.5 <= p < 5): g as a polynomial in
 # t - G32_MID, t = G_K / (G_K + p), coefficients rounded to single precision.
 G32_LO, G32_HI = 0.5, 5.0
 G32_DEG = 7
 
 
-def series_coeffs():
+def cheb_nodes(a, b, n):
+    return [(a + b) / 2 + (b - a) / 2 * mp.cos(mp.pi * (j + mp.mpf(1) / 2) / n) for j in range(n)]
+
+
+def F_exact(q):
+    q = mp.mpf(q)
     sp = mp.sqrt(mp.pi)
-    c1 = [(-1) ** n * mp.mpf(8 * (n + 1) * (n + 2)) / (3 * (2 * n + 1) * mp.factorial(n)) / sp
-          for n in range(SERIES_TERMS)]
-    c2 = [(-1) ** n * mp.mpf(16 * (n + 2) * (n + 3)) / (3 * (2 * n + 3) * mp.factorial(n)) / sp
-          for n in range(SERIES_TERMS)]
-    return c1, c2
+    if q == 0:
+        return 16 / (3 * sp), 32 / (3 * sp)
+    s1, s2 = s_exact(mp.sqrt(q))
+    p = mp.sqrt(q)
+    return s1 / p, s2 / p ** 3
+
+
+def series_coeffs():
+    """Interpolants of F1, F2 at Chebyshev nodes of [0, SERIES_Q_MAX], in x = q - SERIES_MID."""
+    xs = cheb_nodes(mp.mpf(0), mp.mpf(SERIES_Q_MAX), SERIES_DEG + 1)
+    A = mp.matrix([[(x - SERIES_MID) ** i for i in range(SERIES_DEG + 1)] for x in xs])
+    vals = [F_exact(x) for x in xs]
+    c1 = mp.lu_solve(A, mp.matrix([v[0] for v in vals]))
+    c2 = mp.lu_solve(A, mp.matrix([v[1] for v in vals]))
+    return [c for c in c1], [c for c in c2]
 
 
 def g_exact(p):
@@ -57,13 +75,32 @@ def g_exact(p):
     return mp.exp(p * p) * mp.erfc(p)
 
 
+def g_tmid():
+    return float((G_K / (G_K + G_HI) + G_K / (G_K + G_LO)) / 2)
+
+
 def g_coeffs():
-    ta, tb = G_K / (G_K + G_HI), G_K / (G_K + G_LO)
-    nodes = [mp.cos(mp.pi * (j + mp.mpf(1) / 2) / (G_DEG + 1)) for j in range(G_DEG + 1)]
-    ts = [(ta + tb) / 2 + (tb - ta) / 2 * c for c in nodes]
-    A = mp.matrix([[t ** i for i in range(G_DEG + 1)] for t in ts])
-    y = mp.matrix([g_exact(G_K / t - G_K) for t in ts])
-    return [c for c in mp.lu_solve(A, y)]
+    """Least squares (40-digit normal equations) of g in t - t_mid, weighted by e^{-p^2}."""
+    mid = mp.mpf(g_tmid())
+    ps = [mp.mpf(G_LO) + (G_HI - G_LO) * (1 - mp.cos(mp.pi * (k + mp.mpf(1) / 2) / 600)) / 2
+          for k in range(600)]
+    rows, rhs = [], []
+    for p in ps:
+        w = mp.exp(-p * p)
+        t = G_K / (G_K + p) - mid
+        rows.append([w * t ** i for i in range(G_DEG + 1)])
+        rhs.append(w * g_exact(p))
+    A = mp.matrix(rows)
+    y = mp.matrix(rhs)
+    return [c for c in mp.lu_solve(A.T * A, A.T * y)]
+
+
+def exp_coeffs():
+    """Interpolant of e^x at Chebyshev nodes of [-ln2/2, ln2/2] (monomial coefficients)."""
+    a = mp.log(2) / 2
+    xs = cheb_nodes(-a, a, EXP_DEG + 1)
+    A = mp.matrix([[x ** i for i in range(EXP_DEG + 1)] for x in xs])
+    return [c for c in mp.lu_solve(A, mp.matrix([mp.exp(x) for x in xs]))]
 
 
 def g32_coeffs():
@@ -107,27 +144,39 @@ def ln2_split():
     return hi, lo
 
 
-def check(c1, c2, gc):
+def check(c1, c2, gc, ec):
     """Max errors of the double-precision evaluation (numpy mirrors the device arithmetic)."""
-    mp.mp.dps = 40
     rep = {}
     q = np.linspace(0.0, SERIES_Q_MAX, 2001)
-    F1 = horner(c1, q)
-    F2 = horner(c2, q)
+    F1 = horner(c1, q - SERIES_MID)
+    F2 = horner(c2, q - SERIES_MID)
     e1 = e2 = 0.0
-    for qi, a, b in zip(q[::10], F1[::10], F2[::10]):
-        p = mp.sqrt(mp.mpf(float(qi)))
-        if p == 0:
-            r1, r2 = 16 / (3 * mp.sqrt(mp.pi)), 32 / (3 * mp.sqrt(mp.pi))
-        else:
-            s1, s2 = s_exact(p)
-            r1, r2 = s1 / p, s2 / p ** 3
+    for qi, a, b in zip(q[::5], F1[::5], F2[::5]):
+        r1, r2 = F_exact(float(qi))
         e1 = max(e1, float(abs(a - r1) / r1))
         e2 = max(e2, float(abs(b - r2) / r2))
     rep["series_rel_F1"], rep["series_rel_F2"] = e1, e2
     p = np.linspace(G_LO, G_HI, 3001)
-    gv = horner(gc, G_K / (G_K + p))
-    rep["g_abs"] = max(float(abs(mp.mpf(float(a)) - g_exact(float(x)))) for x, a in zip(p[::3], gv[::3]))
+    gv = horner(gc, G_K / (G_K + p) - g_tmid())
+    rep["g_weighted_abs"] = max(float(abs(mp.mpf(float(a)) - g_exact(float(x))) * mp.exp(-mp.mpf(float(x)) ** 2))
+                                for x, a in zip(p[::3], gv[::3]))
+    a = float(mp.log(2) / 2)
+    x = np.linspace(-a, a, 2001)
+    ev = horner(ec, x)
+    rep["exp_rel"] = max(float(abs(mp.mpf(float(v)) - mp.exp(float(xx))) / mp.exp(float(xx)))
+                         for xx, v in zip(x[::5], ev[::5]))
+    # the assembled smoothing factors on 1 <= p < 6.9 (double evaluation, exact e^{-q})
+    worst = 0.0
+    c0 = 2.0 / (3.0 * np.sqrt(np.pi))
+    for pp in np.linspace(G_LO, G_HI, 400):
+        qq = pp * pp
+        g = horner(gc, np.array([G_K / (G_K + pp) - g_tmid()]))[0]
+        E = float(mp.exp(-mp.mpf(qq)))
+        s1 = 1.0 - E * (g + c0 * pp * (2 * qq - 5))
+        s2 = 1.0 - E * (g + c0 * pp * (4 * qq * qq - 14 * qq + 3))
+        x1, x2 = s_exact(pp)
+        worst = max(worst, float(abs(s1 - x1) / x1), float(abs(s2 - x2) / x2))
+    rep["s_rel_1_to_6.9"] = worst
     return rep
 
 
@@ -139,33 +188,36 @@ def main():
     mp.mp.dps = 40
     c1, c2 = series_coeffs()
     gc = g_coeffs()
+    ec = exp_coeffs()
     hi, lo = ln2_split()
-    rep = check(c1, c2, gc)
+    rep = check(c1, c2, gc, ec)
     g32, g32_mid, g32_err = g32_coeffs()
     rep["g32_abs"] = g32_err
     for k, v in rep.items():
         print(f"{k}: {v:.3e}")
     lines = [
         "// sl_smoothing_coeffs.h -- GENERATED by gen_smoothing.py; do not edit.",
-        "// Constants of the double-precision smoothing factors s1, s2 (Sec. 3.4).",
-        f"// Achieved max errors (double evaluation): series F1 rel {rep['series_rel_F1']:.2e},"
-        f" F2 rel {rep['series_rel_F2']:.2e}; g abs {rep['g_abs']:.2e}.",
+        "// Constants of the device evaluation of the smoothing factors s1, s2 (Sec. 3.4).",
+        f"// Achieved max errors (double evaluation): F1 rel {rep['series_rel_F1']:.2e},"
+        f" F2 rel {rep['series_rel_F2']:.2e}; e^-q |g - fit| {rep['g_weighted_abs']:.2e};"
+        f" exp rel {rep['exp_rel']:.2e}; s on [1, 6.9) rel {rep['s_rel_1_to_6.9']:.2e}.",
         "#pragma once",
         "namespace sl {",
         f"constexpr double kSeriesQMax = {SERIES_Q_MAX!r};",
-        f"constexpr int kSeriesTerms = {SERIES_TERMS};",
-        "// sqrt(pi)^-1 * (-1)^n 8 (n+1)(n+2) / (3 (2n+1) n!): F1(q) = sum kF1[n] q^n",
-        "constexpr double kF1[kSeriesTerms] = {" + ", ".join(fmt(c) for c in c1) + "};",
-        "// sqrt(pi)^-1 * (-1)^n 16 (n+2)(n+3) / (3 (2n+3) n!): F2(q) = sum kF2[n] q^n",
-        "constexpr double kF2[kSeriesTerms] = {" + ", ".join(fmt(c) for c in c2) + "};",
+        f"constexpr double kSeriesMid = {SERIES_MID!r};",
+        f"constexpr int kSeriesDeg = {SERIES_DEG};",
+        "// F1(q) = s1(p)/p ~= sum kF1[n] (q - kSeriesMid)^n on 0 <= q < kSeriesQMax",
+        "constexpr double kF1[kSeriesDeg + 1] = {" + ", ".join(fmt(c) for c in c1) + "};",
+        "// F2(q) = s2(p)/p^3 ~= sum kF2[n] (q - kSeriesMid)^n on 0 <= q < kSeriesQMax",
+        "constexpr double kF2[kSeriesDeg + 1] = {" + ", ".join(fmt(c) for c in c2) + "};",
         f"constexpr double kGK = {G_K!r};   // t = kGK / (kGK + p)",
+        f"constexpr double kGMid = {g_tmid()!r};",
         f"constexpr int kGDeg = {G_DEG};",
-        "// g(p) = exp(p^2) erfc(p) ~= sum kG[i] t^i on 0.5 <= p <= 6.9",
+        f"// g(p) = exp(p^2) erfc(p) ~= sum kG[i] (t - kGMid)^i on {G_LO} <= p <= {G_HI}",
         "constexpr double kG[kGDeg + 1] = {" + ", ".join(fmt(c) for c in gc) + "};",
         f"constexpr int kExpDeg = {EXP_DEG};",
-        "// Taylor coefficients 1/k! of e^x",
-        "constexpr double kExpC[kExpDeg + 1] = {" +
-        ", ".join(fmt(mp.mpf(1) / mp.factorial(k)) for k in range(EXP_DEG + 1)) + "};",
+        "// e^x ~= sum kExpC[k] x^k on |x| <= ln2/2",
+        "constexpr double kExpC[kExpDeg + 1] = {" + ", ".join(fmt(c) for c in ec) + "};",
         f"constexpr double kLn2Hi = {hi!r};",
         f"constexpr double kLn2Lo = {lo!r};",
         f"constexpr double kLog2E = {float(1 / mp.log(2))!r};",

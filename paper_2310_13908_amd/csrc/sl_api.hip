@@ -62,12 +62,11 @@ struct EvalWorkspace {
     SrcOut so;
     TgtOut to;
     double *part;
-    double *part_near;
     void *tblock;
 };
 
 static size_t carve(char *base, EvalWorkspace &w, int64_t n_sort, int64_t np_s, int64_t np_t,
-                    bool distinct, bool mixed, bool vard, int n_splits, int near_ways)
+                    bool distinct, bool mixed, bool vard, int n_ways)
 {
     size_t off = 0;
     auto take = [&](size_t bytes) -> char * {
@@ -79,14 +78,16 @@ static size_t carve(char *base, EvalWorkspace &w, int64_t n_sort, int64_t np_s, 
     if (base) carve_sort_scratch(sort_base, n_sort, w.ps);
     memset(&w.so, 0, sizeof(w.so));
     memset(&w.to, 0, sizeof(w.to));
-    w.so.x = (double *)take(np_s * 8); w.so.y = (double *)take(np_s * 8); w.so.z = (double *)take(np_s * 8);
-    w.so.gx = (double *)take(np_s * 8); w.so.gy = (double *)take(np_s * 8); w.so.gz = (double *)take(np_s * 8);
-    if (mixed) {
-        w.so.x32 = (float *)take(np_s * 4); w.so.y32 = (float *)take(np_s * 4); w.so.z32 = (float *)take(np_s * 4);
-        w.so.gx32 = (float *)take(np_s * 4); w.so.gy32 = (float *)take(np_s * 4); w.so.gz32 = (float *)take(np_s * 4);
-    }
+    w.so.d = (double *)take(np_s * 64);
+    if (mixed) w.so.f32 = (float *)take(np_s * 32);
     w.so.sphere = (double4 *)take(np_s / kCluster * sizeof(double4));
-    if (!distinct) w.so.perm = (int32_t *)take(np_s * 4);
+    if (!distinct) {   // targets = sources: structure-of-arrays positions for the target side
+        w.so.x = (double *)take(np_s * 8); w.so.y = (double *)take(np_s * 8); w.so.z = (double *)take(np_s * 8);
+        if (mixed) {
+            w.so.x32 = (float *)take(np_s * 4); w.so.y32 = (float *)take(np_s * 4); w.so.z32 = (float *)take(np_s * 4);
+        }
+        w.so.perm = (int32_t *)take(np_s * 4);
+    }
     if (distinct) {
         w.to.x = (double *)take(np_t * 8); w.to.y = (double *)take(np_t * 8); w.to.z = (double *)take(np_t * 8);
         if (mixed) {
@@ -95,8 +96,7 @@ static size_t carve(char *base, EvalWorkspace &w, int64_t n_sort, int64_t np_s, 
         w.to.perm = (int32_t *)take(np_t * 4);
     }
     if (vard) w.to.delta = (double *)take(np_t * 8);
-    w.part = (double *)take((size_t)n_splits * 3 * np_t * 8);
-    w.part_near = (double *)take((size_t)near_ways * 3 * np_t * 8);
+    w.part = (double *)take((size_t)n_ways * 3 * np_t * 8);
     w.tblock = take(tblock_scratch_bytes((int)(np_t / kWave)));   // enough for any R >= 1
     return off;
 }
@@ -196,20 +196,16 @@ sl_status sl_get_stats(sl_ctx *ctx, sl_stats *out)
         std::lock_guard<std::mutex> l(ctx->mu);
         DeviceGuard g(ctx->device);
         for (auto &ev : ctx->timed) {
-            float ms_far = 0.0f, ms_near = 0.0f;
-            SL_HIP(hipEventSynchronize(ev.e2));
-            SL_HIP(hipEventElapsedTime(&ms_far, ev.e0, ev.e1));
-            SL_HIP(hipEventElapsedTime(&ms_near, ev.e1, ev.e2));
-            ctx->far_ms += ms_far;
-            ctx->near_ms += ms_near;
+            float ms = 0.0f;
+            SL_HIP(hipEventSynchronize(ev.e1));
+            SL_HIP(hipEventElapsedTime(&ms, ev.e0, ev.e1));
+            ctx->pair_ms += ms;
             ctx->pair_launches += 1;
-            for (hipEvent_t e : {ev.e0, ev.e1, ev.e2}) ctx->spare_events.push_back(e);
+            for (hipEvent_t e : {ev.e0, ev.e1}) ctx->spare_events.push_back(e);
         }
         ctx->timed.clear();
         out->pair_launches = ctx->pair_launches;
-        out->pair_ms = ctx->far_ms + ctx->near_ms;
-        out->far_ms = ctx->far_ms;
-        out->near_ms = ctx->near_ms;
+        out->pair_ms = ctx->pair_ms;
     }
     server_stats(ctx, out);
     return SL_OK;
@@ -273,11 +269,10 @@ sl_status sl_eval(sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *s
     plan.n_cu = ctx->n_cu;
 
     EvalWorkspace ws;
-    const size_t bytes = carve(nullptr, ws, n_sort, np_s, np_t, !same, mixed, vard, plan.n_splits,
-                               plan.near_ways);
+    const size_t bytes = carve(nullptr, ws, n_sort, np_s, np_t, !same, mixed, vard, plan.n_ways);
     char *base = nullptr;
     SL_HIP(hipMallocAsync((void **)&base, bytes, st));
-    carve(base, ws, n_sort, np_s, np_t, !same, mixed, vard, plan.n_splits, plan.near_ways);
+    carve(base, ws, n_sort, np_s, np_t, !same, mixed, vard, plan.n_ways);
 
     hipError_t e = launch_bbox(sx, sy, sz, n_src, tx, ty, tz, same ? 0 : n_tgt, ws.ps, st);
     const uint32_t *order = nullptr;
@@ -308,9 +303,7 @@ sl_status sl_eval(sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *s
     tv.n = n_tgt;
 
     PairArgs pa;
-    pa.s = SrcView{ws.so.x, ws.so.y, ws.so.z, ws.so.gx, ws.so.gy, ws.so.gz,
-                   ws.so.x32, ws.so.y32, ws.so.z32, ws.so.gx32, ws.so.gy32, ws.so.gz32,
-                   ws.so.sphere, np_s};
+    pa.s = SrcView{ws.so.d, ws.so.f32, ws.so.sphere, np_s};
     pa.t = tv;
     pa.delta = vard ? 1.0 : delta;
     {
@@ -319,18 +312,15 @@ sl_status sl_eval(sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *s
     }
     // far clusters: s = 1 to the working precision, and (mixed) outside the FP64 zone
     pa.far_cut = mixed ? std::max(kRhoExact32, pa.rho64) : kRhoExact64;
-    pa.clusters_per_split = plan.clusters_per_split;
-    pa.n_splits = plan.n_splits;
     pa.n_tblocks = plan.n_tblocks;
-    pa.near_ways = plan.near_ways;
-    pa.part_near = ws.part_near;
+    pa.n_ways = plan.n_ways;
     pa.part = ws.part;
     pa.bbox = ws.ps.bbox;
     pa.tblock_scratch = ws.tblock;
-    PairTiming tev{nullptr, nullptr, nullptr};
+    PairTiming tev{nullptr, nullptr};
     if (ctx->timing && e == hipSuccess) {
         std::lock_guard<std::mutex> l(ctx->mu);
-        for (hipEvent_t *ev : {&tev.e0, &tev.e1, &tev.e2}) {
+        for (hipEvent_t *ev : {&tev.e0, &tev.e1}) {
             if (!ctx->spare_events.empty()) {
                 *ev = ctx->spare_events.back();
                 ctx->spare_events.pop_back();
@@ -339,14 +329,13 @@ sl_status sl_eval(sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *s
             }
         }
     }
-    if (e == hipSuccess) e = launch_pair(pa, plan, mixed, vard, st, tev.e2 ? &tev : nullptr);
-    if (tev.e2 && e == hipSuccess) {
+    if (e == hipSuccess) e = launch_pair(pa, plan, mixed, vard, st, tev.e1 ? &tev : nullptr);
+    if (tev.e1 && e == hipSuccess) {
         std::lock_guard<std::mutex> l(ctx->mu);
         ctx->timed.push_back(tev);
     }
     if (e == hipSuccess)
-        e = launch_reduce(ws.part, plan.n_splits, ws.part_near, plan.near_ways, np_t, tv.perm,
-                          1.0 / (8.0 * M_PI * mu), ux, uy, uz, st);
+        e = launch_reduce(ws.part, plan.n_ways, np_t, tv.perm, 1.0 / (8.0 * M_PI * mu), ux, uy, uz, st);
     const hipError_t ef = hipFreeAsync(base, st);
     if (e != hipSuccess) return hip_fail(e, "sl_eval: kernel launch");
     if (ef != hipSuccess) return hip_fail(ef, "sl_eval: hipFreeAsync");

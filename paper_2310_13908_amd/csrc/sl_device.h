@@ -8,8 +8,8 @@
 // Far from the target (r/delta >= 6.9) both smoothing factors equal 1 to double precision
 // (|s - 1| < 2^-53; at r/delta >= 5, |s - 1| < 2^-24), so the far pair is the plain
 // Stokeslet K1 = 1/r, K2 = 1/r^3: 28 flops, no erf/exp.  Nearer pairs apply the smoothing in
-// double precision (smoothing64 below: a power series near r = 0, otherwise one exp and a
-// fitted scaled complementary error function).
+// double precision (below: a fitted polynomial in (r/delta)^2 for r < delta, otherwise one exp
+// and a fitted scaled complementary error function).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -84,7 +84,7 @@ __device__ __forceinline__ double sconst(double c)
 }
 
 // e^{-q} for 0 <= q <= 700: q = n ln2 + f with |f| <= ln2/2, e^{-q} = 2^-n e^{-f}, e^{-f} by
-// its Taylor series (degree 13: truncation below 2^-53 relative).
+// a degree-11 polynomial fitted on |f| <= ln2/2 (relative error below 2^-52).
 __device__ __forceinline__ double exp_neg64(double q)
 {
     const double n = rint(q * kLog2E);
@@ -95,46 +95,47 @@ __device__ __forceinline__ double exp_neg64(double q)
     return ldexp(p, -(int)n);
 }
 
-// Smoothed kernel factors K1 = s1(p)/r, K2 = s2(p)/r^3 for p = r/delta < 6.9 (Sec. 3.4), given
-// r2 = r^2 and ri = 1/r (ri is not used when r = 0).
-//   p^2 < 0.25: K1 = F1(p^2)/delta, K2 = F2(p^2)/delta^3 with the power series of s1/p and s2/p^3
-//               (no cancellation, and the r = 0 limits 16/(3 sqrt(pi) delta), 32/(3 sqrt(pi)
-//               delta^3) come out at q = 0);
-//   otherwise:  s = 1 - e^{-q} (g(p) + P(p)), g(p) = e^{p^2} erfc(p) from its fitted polynomial
-//               in t = 3/(3+p), P1 = (2/(3 sqrt(pi))) p (2q - 5),
-//               P2 = (2/(3 sqrt(pi))) p (4q^2 - 14q + 3).
-__device__ __forceinline__ void smoothing64(double r2, double ri, double ri2, const DeltaC &dc,
-                                            double &K1, double &K2)
+// Smoothed kernel factors for q = (r/delta)^2 < 1 (Sec. 3.4): K1 = F1(q)/delta,
+// K2 = F2(q)/delta^3 with F1 = s1(p)/p, F2 = s2(p)/p^3 as polynomials in q - 1/2.  No 1/r is
+// needed, there is no cancellation, and the r = 0 limits 16/(3 sqrt(pi) delta),
+// 32/(3 sqrt(pi) delta^3) come out at q = 0.
+__device__ __forceinline__ void smoothing_small64(double q, const DeltaC &dc, double &K1, double &K2)
 {
-    const double q = r2 * dc.id2;
-    if (q < kSeriesQMax) {
-        double f1 = kF1[kSeriesTerms - 1], f2 = kF2[kSeriesTerms - 1];
+    const double x = q - kSeriesMid;
+    double f1 = kF1[kSeriesDeg], f2 = kF2[kSeriesDeg];
 #pragma unroll
-        for (int k = kSeriesTerms - 2; k >= 0; --k) {
-            f1 = fma(f1, q, sconst(kF1[k]));
-            f2 = fma(f2, q, sconst(kF2[k]));
-        }
-        K1 = f1 * dc.id;
-        K2 = f2 * dc.id3;
-    } else {
-        const double p = (r2 * ri) * dc.id;
-        const double E = exp_neg64(q);
-        const double den = kGK + p;
-        double y = __builtin_amdgcn_rcp(den);      // refined twice: 1/den to ~1 ulp
-        double e = fma(-den, y, 1.0);
-        y = fma(y, e, y);
-        e = fma(-den, y, 1.0);
-        y = fma(y, e, y);
-        const double t = kGK * y;
-        double g = kG[kGDeg];
-#pragma unroll
-        for (int i = kGDeg - 1; i >= 0; --i) g = fma(g, t, sconst(kG[i]));
-        const double c0p = kC0 * p;
-        const double A1 = fma(c0p, fma(2.0, q, -5.0), g);
-        const double A2 = fma(c0p, fma(q, fma(4.0, q, -14.0), 3.0), g);
-        K1 = ri * fma(-E, A1, 1.0);
-        K2 = (ri * ri2) * fma(-E, A2, 1.0);
+    for (int k = kSeriesDeg - 1; k >= 0; --k) {
+        f1 = fma(f1, x, sconst(kF1[k]));
+        f2 = fma(f2, x, sconst(kF2[k]));
     }
+    K1 = f1 * dc.id;
+    K2 = f2 * dc.id3;
+}
+
+// Smoothed kernel factors for 1 <= q, p = r/delta < 6.9, given r2 = r^2 and ri = 1/r:
+// s = 1 - e^{-q} (g(p) + P(p)), g(p) = e^{p^2} erfc(p) from its fitted polynomial in
+// t = 3/(3+p), P1 = (2/(3 sqrt(pi))) p (2q - 5), P2 = (2/(3 sqrt(pi))) p (4q^2 - 14q + 3);
+// K1 = s1/r, K2 = s2/r^3.
+__device__ __forceinline__ void smoothing_large64(double r2, double q, double ri, double ri2,
+                                                  const DeltaC &dc, double &K1, double &K2)
+{
+    const double p = (r2 * ri) * dc.id;
+    const double E = exp_neg64(q);
+    const double den = kGK + p;
+    double y = __builtin_amdgcn_rcp(den);      // refined twice: 1/den to ~1 ulp
+    double e = fma(-den, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-den, y, 1.0);
+    y = fma(y, e, y);
+    const double t = fma(kGK, y, -kGMid);
+    double g = kG[kGDeg];
+#pragma unroll
+    for (int i = kGDeg - 1; i >= 0; --i) g = fma(g, t, sconst(kG[i]));
+    const double c0p = kC0 * p;
+    const double A1 = fma(c0p, fma(2.0, q, -5.0), g);
+    const double A2 = fma(c0p, fma(q, fma(4.0, q, -14.0), 3.0), g);
+    K1 = ri * fma(-E, A1, 1.0);
+    K2 = (ri * ri2) * fma(-E, A2, 1.0);
 }
 
 // Regularized pair in double precision: the exact kernel for any r >= 0.
@@ -149,7 +150,140 @@ __device__ __forceinline__ void near_pair64(double tx, double ty, double tz,
     const double ri = rsqrt64(r2 > 0.0 ? r2 : 1.0);
     const double ri2 = ri * ri;
     double K1 = ri, K2 = ri * ri2;
-    if (r2 < dc.cut2) smoothing64(r2, ri, ri2, dc, K1, K2);
+    if (r2 < dc.cut2) {
+        const double q = r2 * dc.id2;
+        if (q < kSeriesQMax) smoothing_small64(q, dc, K1, K2);
+        else smoothing_large64(r2, q, ri, ri2, dc, K1, K2);
+    }
+    const double gd = fma(gx, dx, fma(gy, dy, gz * dz));
+    const double c = gd * K2;
+    ax = fma(K1, gx, fma(c, dx, ax));
+    ay = fma(K1, gy, fma(c, dy, ay));
+    az = fma(K1, gz, fma(c, dz, az));
+}
+
+// One source against the R targets of a lane, in double precision: near_pair64 for each target,
+// with the smoothing evaluated for all R targets together wherever one lane of the wavefront
+// needs it, so that each polynomial coefficient is materialized once for R targets.
+template <int R>
+__device__ __forceinline__ void near_pairs64(const double (&tx)[R], const double (&ty)[R],
+                                             const double (&tz)[R], double sx, double sy, double sz,
+                                             double gx, double gy, double gz, const DeltaC (&dc)[R],
+                                             double (&ax)[R], double (&ay)[R], double (&az)[R])
+{
+    double dx[R], dy[R], dz[R], r2[R], ri[R], q[R], K1[R], K2[R];
+    bool sm[R], lg[R];
+    bool any_sm = false, any_lg = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        dx[r] = tx[r] - sx;
+        dy[r] = ty[r] - sy;
+        dz[r] = tz[r] - sz;
+        r2[r] = fma(dx[r], dx[r], fma(dy[r], dy[r], dz[r] * dz[r]));
+        ri[r] = rsqrt64(r2[r] > 0.0 ? r2[r] : 1.0);
+        K1[r] = ri[r];
+        K2[r] = ri[r] * ri[r] * ri[r];
+        q[r] = r2[r] * dc[r].id2;
+        sm[r] = q[r] < kSeriesQMax;
+        lg[r] = !sm[r] && r2[r] < dc[r].cut2;
+        any_sm = any_sm || sm[r];
+        any_lg = any_lg || lg[r];
+    }
+    if (__builtin_amdgcn_ballot_w64(any_sm)) {
+        double x[R], f1[R], f2[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            x[r] = fmin(q[r], kSeriesQMax) - kSeriesMid;
+            f1[r] = kF1[kSeriesDeg];
+            f2[r] = kF2[kSeriesDeg];
+        }
+#pragma unroll
+        for (int k = kSeriesDeg - 1; k >= 0; --k) {
+            const double c1 = sconst(kF1[k]), c2 = sconst(kF2[k]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                f1[r] = fma(f1[r], x[r], c1);
+                f2[r] = fma(f2[r], x[r], c2);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            K1[r] = sm[r] ? f1[r] * dc[r].id : K1[r];
+            K2[r] = sm[r] ? f2[r] * dc[r].id3 : K2[r];
+        }
+    }
+    if (__builtin_amdgcn_ballot_w64(any_lg)) {
+        double p[R], n[R], f[R], e[R], y[R], t[R], g[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double qq = fmin(fmax(q[r], kSeriesQMax), kRhoExact64 * kRhoExact64);
+            p[r] = (r2[r] * ri[r]) * dc[r].id;
+            n[r] = rint(qq * kLog2E);
+            f[r] = fma(-n[r], kLn2Lo, fma(-n[r], kLn2Hi, qq));
+            e[r] = kExpC[kExpDeg];
+            const double den = kGK + p[r];
+            double yy = __builtin_amdgcn_rcp(den);
+            double ee = fma(-den, yy, 1.0);
+            yy = fma(yy, ee, yy);
+            ee = fma(-den, yy, 1.0);
+            y[r] = fma(yy, ee, yy);
+            t[r] = fma(kGK, y[r], -kGMid);
+            g[r] = kG[kGDeg];
+        }
+#pragma unroll
+        for (int k = kExpDeg - 1; k >= 0; --k) {
+            const double c = sconst(kExpC[k]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) e[r] = fma(e[r], -f[r], c);
+        }
+#pragma unroll
+        for (int i = kGDeg - 1; i >= 0; --i) {
+            const double c = sconst(kG[i]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) g[r] = fma(g[r], t[r], c);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double E = ldexp(e[r], -(int)n[r]);
+            const double qq = fmin(fmax(q[r], kSeriesQMax), kRhoExact64 * kRhoExact64);
+            const double c0p = kC0 * p[r];
+            const double A1 = fma(c0p, fma(2.0, qq, -5.0), g[r]);
+            const double A2 = fma(c0p, fma(qq, fma(4.0, qq, -14.0), 3.0), g[r]);
+            K1[r] = lg[r] ? ri[r] * fma(-E, A1, 1.0) : K1[r];
+            K2[r] = lg[r] ? (ri[r] * ri[r] * ri[r]) * fma(-E, A2, 1.0) : K2[r];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double gd = fma(gx, dx[r], fma(gy, dy[r], gz * dz[r]));
+        const double c = gd * K2[r];
+        ax[r] = fma(K1[r], gx, fma(c, dx[r], ax[r]));
+        ay[r] = fma(K1[r], gy, fma(c, dy[r], ay[r]));
+        az[r] = fma(K1[r], gz, fma(c, dz[r], az[r]));
+    }
+}
+
+// Pair of the mixed path's double-precision zone (p < rho64, including r = 0): as near_pair64,
+// without 1/r where q < 1 (always so for rho64 <= 1).
+__device__ __forceinline__ void zone_pair64(double tx, double ty, double tz,
+                                            double sx, double sy, double sz,
+                                            double gx, double gy, double gz,
+                                            const DeltaC &dc,
+                                            double &ax, double &ay, double &az)
+{
+    const double dx = tx - sx, dy = ty - sy, dz = tz - sz;
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const double q = r2 * dc.id2;
+    double K1, K2;
+    if (q < kSeriesQMax) {
+        smoothing_small64(q, dc, K1, K2);
+    } else {
+        const double ri = rsqrt64(r2);
+        const double ri2 = ri * ri;
+        K1 = ri;
+        K2 = ri * ri2;
+        if (r2 < dc.cut2) smoothing_large64(r2, q, ri, ri2, dc, K1, K2);
+    }
     const double gd = fma(gx, dx, fma(gy, dy, gz * dz));
     const double c = gd * K2;
     ax = fma(K1, gx, fma(c, dx, ax));
@@ -175,7 +309,7 @@ __device__ __forceinline__ DeltaC32 make_delta32(double delta, double rho64)
 }
 
 // Smoothed K1 = s1(p)/r, K2 = s2(p)/r^3 in single precision for 0.5 <= p < 5 (no cancellation
-// there: s1 >= 1.5 p, s2 >= 0.55): s = 1 - e^{-q} (g(p) + P(p)) as in smoothing64, with the
+// there: s1 >= 1.5 p, s2 >= 0.55): s = 1 - e^{-q} (g(p) + P(p)) as in smoothing_large64, with the
 // hardware exp2 and reciprocal and a degree-7 fit of g.
 __device__ __forceinline__ void smoothing32(float r2, float ri, const DeltaC32 &dc, float &K1,
                                             float &K2)
@@ -197,7 +331,9 @@ __device__ __forceinline__ void smoothing32(float r2, float ri, const DeltaC32 &
 // Near pair of the mixed path.  p < rho64 (including r = 0): the double-precision kernel,
 // accumulated in (ax, ay, az).  rho64 <= p < 5: smoothed kernel in single precision; p >= 5:
 // plain Stokeslet in single precision; both accumulated in (px, py, pz).  The zone is decided
-// from the single-precision distance.
+// from the single-precision distance.  The smoothing and the double-precision zone run only when
+// some lane of the wavefront needs them (wave-uniform tests), so a source that is farther than
+// 5 delta from all 64 targets of the wavefront costs what a far pair costs.
 __device__ __forceinline__ void near_pair_mixed(float tx32, float ty32, float tz32, double tx,
                                                 double ty, double tz, float sx32, float sy32,
                                                 float sz32, float gx32, float gy32, float gz32,
@@ -208,18 +344,26 @@ __device__ __forceinline__ void near_pair_mixed(float tx32, float ty32, float tz
 {
     const float dx = tx32 - sx32, dy = ty32 - sy32, dz = tz32 - sz32;
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-    if (r2 < dc32.cut2_64) {
-        near_pair64(tx, ty, tz, sx, sy, sz, gx, gy, gz, dc64, ax, ay, az);
-    } else {
-        const float ri = __builtin_amdgcn_rsqf(r2);
-        float K1 = ri, K2 = ri * ri * ri;
-        if (r2 < dc32.cut2_5) smoothing32(r2, ri, dc32, K1, K2);
-        const float gd = fmaf(gx32, dx, fmaf(gy32, dy, gz32 * dz));
-        const float c = gd * K2;
-        px = fmaf(K1, gx32, fmaf(c, dx, px));
-        py = fmaf(K1, gy32, fmaf(c, dy, py));
-        pz = fmaf(K1, gz32, fmaf(c, dz, pz));
+    const bool z64 = r2 < dc32.cut2_64;
+    const bool z5 = r2 < dc32.cut2_5;
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    float K1 = ri, K2 = ri * ri * ri;
+    if (__builtin_amdgcn_ballot_w64(z5)) {
+        float S1, S2;
+        smoothing32(r2, ri, dc32, S1, S2);
+        K1 = z5 ? S1 : K1;
+        K2 = z5 ? S2 : K2;
     }
+    K1 = z64 ? 0.0f : K1;
+    K2 = z64 ? 0.0f : K2;
+    if (__builtin_amdgcn_ballot_w64(z64)) {
+        if (z64) zone_pair64(tx, ty, tz, sx, sy, sz, gx, gy, gz, dc64, ax, ay, az);
+    }
+    const float gd = fmaf(gx32, dx, fmaf(gy32, dy, gz32 * dz));
+    const float c = gd * K2;
+    px = fmaf(K1, gx32, fmaf(c, dx, px));
+    py = fmaf(K1, gy32, fmaf(c, dy, py));
+    pz = fmaf(K1, gz32, fmaf(c, dz, pz));
 }
 
 // Plain Stokeslet pair in single precision (far zone of the mixed path).

@@ -35,13 +35,14 @@ inline int64_t round_up(int64_t n, int64_t m) { return (n + m - 1) / m * m; }
 // Sorted, padded point sets ("packed" layout in HBM)
 // ---------------------------------------------------------------------------------------
 // Sources after the spatial sort: np = round_up(n, kPad) entries; entries n..np-1 repeat the
-// last real node with zero density.  Clusters of 64 consecutive sources carry a bounding
-// sphere (centre x, y, z, radius).
+// last real node with zero density.  Each source is one record of 8 words, x, y, z, gx, gy, gz,
+// 0, 0 (g = w f), so that the pair kernel reads a source with one wide scalar load at a
+// constant offset.  Clusters of 64 consecutive sources carry a bounding sphere (centre x, y, z,
+// radius).
 struct SrcView {
-    const double *x, *y, *z;       // sorted positions
-    const double *gx, *gy, *gz;    // sorted w * f
-    const float *x32, *y32, *z32;  // positions minus `centre`, single precision (mixed only)
-    const float *gx32, *gy32, *gz32;
+    const double *d;               // [np][8] double precision
+    const float *f32;              // [np][8] single precision, positions minus the box centre
+                                   // (mixed only)
     const double4 *sphere;         // [np / 64]
     int64_t np;
 };
@@ -63,20 +64,17 @@ struct PairArgs {
     double delta;            // scalar delta when t.delta == nullptr
     double far_cut;          // cluster far test: gap >= far_cut * delta_max
     double rho64;            // mixed path: pairs with r/delta below this are summed in FP64
-    int64_t clusters_per_split;
-    int n_splits;
     int n_tblocks;
-    int near_ways;           // K: near clusters of a block are dealt out to K waves by rank
-    double *part;            // [n_splits][3][t.np] far partial sums (unscaled)
-    double *part_near;       // [near_ways][3][t.np] near partial sums (unscaled)
+    int n_ways;              // K: the clusters of a target block are dealt out to K waves by rank
+    double *part;            // [n_ways][3][t.np] partial sums (unscaled)
     const double *bbox;      // [6] box of all points (min xyz, max xyz): bounds the rounding
                              // of the single-precision positions in the mixed path
     void *tblock_scratch;    // tblock_scratch_bytes(n_tblocks): per-target-block spheres
 };
 
-// Optional events recorded around the far kernel (e0 .. e1) and the near kernel (e1 .. e2).
+// Optional events recorded around the pair kernel.
 struct PairTiming {
-    hipEvent_t e0, e1, e2;
+    hipEvent_t e0, e1;
 };
 size_t tblock_scratch_bytes(int n_tblocks);
 
@@ -84,19 +82,16 @@ size_t tblock_scratch_bytes(int n_tblocks);
 struct PairPlan {
     int R;                   // targets per lane
     int n_tblocks;
-    int n_splits;
-    int64_t clusters_per_split;
-    int near_ways;
-    int n_cu;                // compute units: the work loops launch an occupancy-sized grid
+    int n_ways;
+    int n_cu;                // compute units: the work loop launches an occupancy-sized grid
 };
 
 PairPlan plan_pairs(int64_t np_src, int64_t np_tgt, int R, int waves_wanted);
 
 hipError_t launch_pair(const PairArgs &a, const PairPlan &p, bool mixed, bool var_delta,
                        hipStream_t st, const PairTiming *tm);
-hipError_t launch_reduce(const double *part, int n_splits, const double *part_near, int near_ways,
-                         int64_t np, const int32_t *perm, double scale, double *ux, double *uy,
-                         double *uz, hipStream_t st);
+hipError_t launch_reduce(const double *part, int n_ways, int64_t np, const int32_t *perm,
+                         double scale, double *ux, double *uy, double *uz, hipStream_t st);
 hipError_t launch_fill_zero(double *ux, double *uy, double *uz, int64_t n, hipStream_t st);
 
 // ---------------------------------------------------------------------------------------
@@ -105,7 +100,8 @@ hipError_t launch_fill_zero(double *ux, double *uy, double *uz, int64_t n, hipSt
 struct PackScratch {
     uint32_t *keys[2];
     uint32_t *vals[2];
-    uint32_t *counts;        // [256 * n_chunks]
+    uint32_t *counts[3];     // [256 * n_chunks] digit counts of each sort pass
+    int64_t n_counts;
     double *bbox_part;       // [kBboxBlocks * 6]
     double *bbox;            // [6]: min x, y, z, max x, y, z
     double *centre;          // [3]: bounding-box centre (origin of the single-precision copies)
@@ -123,8 +119,10 @@ hipError_t launch_sort_points(const double *x, const double *y, const double *z,
                               const PackScratch &ps, const uint32_t **order, hipStream_t st);
 
 struct SrcOut {
-    double *x, *y, *z, *gx, *gy, *gz;
-    float *x32, *y32, *z32, *gx32, *gy32, *gz32;   // nullptr unless mixed
+    double *d;                                      // [np][8] source records
+    float *f32;                                     // [np][8] single-precision records or nullptr
+    double *x, *y, *z;                              // optional structure-of-arrays positions
+    float *x32, *y32, *z32;                         // (targets = sources), nullptr if unused
     double4 *sphere;
     int32_t *perm;                                  // optional: sorted -> caller index (-1 pad)
 };
@@ -176,5 +174,5 @@ struct sl_ctx {
     std::vector<sl::PairTiming> timed;   // recorded, not yet read
     std::vector<hipEvent_t> spare_events;
     uint64_t pair_launches = 0;
-    double far_ms = 0.0, near_ms = 0.0;
+    double pair_ms = 0.0;
 };

@@ -4,10 +4,12 @@
 // "far" (plain Stokeslet, no erf/exp) or "near" (regularized), which only pays off when
 // consecutive points are close in space.  Packing therefore:
 //   1. takes the bounding box of all points (two-pass, deterministic),
-//   2. orders the points along a 30-bit Morton curve (stable LSD radix sort, 8-bit digits),
+//   2. orders the points along a 24-bit Morton curve (stable LSD radix sort, three passes of
+//      8-bit digits; each pass's digit histogram is counted by the kernel that writes the
+//      pass's input, so a pass is two launches: scan and scatter),
 //   3. gathers positions and the packed density g = w f (the trapezoid-POU weight of
-//      Sec. 3.3 folded into the force) into padded structure-of-arrays buffers, plus the
-//      single-precision copies used by the mixed path (positions relative to the box centre),
+//      Sec. 3.3 folded into the force) into padded per-source records, plus the
+//      single-precision records used by the mixed path (positions relative to the box centre),
 //   4. computes one bounding sphere per cluster of 64 sources.
 // Everything is O(N) and runs on the caller's stream.
 #include "sl_internal.h"
@@ -19,9 +21,11 @@ namespace {
 constexpr int kBboxBlocks = 256;
 constexpr int kBboxThreads = 256;
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 8;
+constexpr int kSortItems = 4;
 constexpr int kSortChunk = kSortThreads * kSortItems;   // elements per block and pass
-constexpr int kMortonBits = 10;                         // per axis
+constexpr int kMortonBits = 8;                          // per axis
+constexpr int kDigitBits = 8;
+constexpr int kPasses = 3 * kMortonBits / kDigitBits;
 
 // ----------------------------------------------------------------------------------------
 // Bounding box
@@ -29,10 +33,13 @@ constexpr int kMortonBits = 10;                         // per axis
 __global__ __launch_bounds__(kBboxThreads) void k_bbox_partial(
     const double *__restrict__ ax, const double *__restrict__ ay, const double *__restrict__ az,
     int64_t na, const double *__restrict__ bx, const double *__restrict__ by,
-    const double *__restrict__ bz, int64_t nb, double *__restrict__ part)
+    const double *__restrict__ bz, int64_t nb, double *__restrict__ part,
+    uint32_t *__restrict__ zero, int64_t n_zero)
 {
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // the first sort's digit counters, counted by k_morton after this kernel
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_zero; i += stride) zero[i] = 0u;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < na + nb; i += stride) {
         double p[3];
         if (i < na) { p[0] = ax[i]; p[1] = ay[i]; p[2] = az[i]; }
@@ -101,48 +108,40 @@ __device__ __forceinline__ uint32_t morton3(uint32_t qx, uint32_t qy, uint32_t q
     return k;
 }
 
+// Keys, identity values, and the digit counts of the first sort pass (counts[digit * nblocks +
+// block], block = i / kSortChunk; integer atomics, so the counts do not depend on their order).
 __global__ __launch_bounds__(256) void k_morton(const double *__restrict__ x,
                                                 const double *__restrict__ y,
                                                 const double *__restrict__ z, int64_t n,
                                                 const double *__restrict__ bbox,
                                                 uint32_t *__restrict__ keys,
-                                                uint32_t *__restrict__ vals)
+                                                uint32_t *__restrict__ vals,
+                                                uint32_t *__restrict__ counts, int nblocks)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t qx = quantize(x[i], bbox[0], bbox[3]);
     const uint32_t qy = quantize(y[i], bbox[1], bbox[4]);
     const uint32_t qz = quantize(z[i], bbox[2], bbox[5]);
-    keys[i] = morton3(qx, qy, qz);
+    const uint32_t k = morton3(qx, qy, qz);
+    keys[i] = k;
     vals[i] = (uint32_t)i;
+    atomicAdd(&counts[(int64_t)(k & 255u) * nblocks + i / kSortChunk], 1u);
 }
 
 // ----------------------------------------------------------------------------------------
 // Stable LSD radix sort of (key, value) pairs, 8-bit digits.
-// Block b owns elements [b * kSortChunk, (b + 1) * kSortChunk) in every pass.
+// Block b owns elements [b * kSortChunk, (b + 1) * kSortChunk) in every pass.  The counts of
+// pass p live in their own buffer, counted by the kernel that writes pass p's input.
 // ----------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *__restrict__ keys,
-                                                          int64_t n, int shift,
-                                                          uint32_t *__restrict__ counts,
-                                                          int nblocks)
-{
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortChunk;
-    for (int k = 0; k < kSortItems; ++k) {
-        const int64_t i = base + k * kSortThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
-    }
-    __syncthreads();
-    counts[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
-}
-
-// Exclusive scan, in place, of `total` counters laid out digit-major (one block).
-__global__ __launch_bounds__(1024) void k_rs_scan(uint32_t *__restrict__ counts, int64_t total)
+// Exclusive scan, in place, of `total` counters laid out digit-major (one block); also clears
+// the counters of the following pass.
+__global__ __launch_bounds__(1024) void k_rs_scan(uint32_t *__restrict__ counts, int64_t total,
+                                                  uint32_t *__restrict__ next)
 {
     __shared__ uint32_t buf[2][1024];
     const int t = threadIdx.x;
+    for (int64_t i = t; i < total; i += 1024) next[i] = 0u;
     const int64_t per = (total + 1023) / 1024;
     const int64_t b = t * per, e = b + per < total ? b + per : total;
     uint32_t s = 0;
@@ -164,10 +163,12 @@ __global__ __launch_bounds__(1024) void k_rs_scan(uint32_t *__restrict__ counts,
     }
 }
 
+// Scatter by the digit at `shift`; when `next` is set, also counts the digit at shift + 8 of
+// every element for the block that owns its new position.
 __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n, int shift,
-    const uint32_t *__restrict__ offs, int nblocks)
+    const uint32_t *__restrict__ offs, int nblocks, uint32_t *__restrict__ next)
 {
     constexpr int kWaves = kSortThreads / kWave;
     __shared__ uint32_t base[256];
@@ -202,6 +203,8 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(
             for (int j = 0; j < w; ++j) off += cnt[j][d];
             kout[off] = key;
             vout[off] = val;
+            if (next)
+                atomicAdd(&next[(int64_t)((key >> (shift + kDigitBits)) & 255u) * nblocks + off / kSortChunk], 1u);
         }
         __syncthreads();
         uint32_t add = 0;
@@ -228,14 +231,17 @@ __global__ __launch_bounds__(256) void k_gather_src(
     const double px = x[idx], py = y[idx], pz = z[idx];
     const double wt = real ? w[idx] : 0.0;
     const double gx = wt * fx[idx], gy = wt * fy[idx], gz = wt * fz[idx];
-    o.x[p] = px; o.y[p] = py; o.z[p] = pz;
-    o.gx[p] = gx; o.gy[p] = gy; o.gz[p] = gz;
-    if (o.x32) {
-        o.x32[p] = (float)(px - centre[0]);
-        o.y32[p] = (float)(py - centre[1]);
-        o.z32[p] = (float)(pz - centre[2]);
-        o.gx32[p] = (float)gx; o.gy32[p] = (float)gy; o.gz32[p] = (float)gz;
+    double4 *rd = reinterpret_cast<double4 *>(o.d + p * 8);
+    rd[0] = make_double4(px, py, pz, gx);
+    rd[1] = make_double4(gy, gz, 0.0, 0.0);
+    const float qx = (float)(px - centre[0]), qy = (float)(py - centre[1]), qz = (float)(pz - centre[2]);
+    if (o.f32) {
+        float4 *rf = reinterpret_cast<float4 *>(o.f32 + p * 8);
+        rf[0] = make_float4(qx, qy, qz, (float)gx);
+        rf[1] = make_float4((float)gy, (float)gz, 0.0f, 0.0f);
     }
+    if (o.x) { o.x[p] = px; o.y[p] = py; o.z[p] = pz; }
+    if (o.x32) { o.x32[p] = qx; o.y32[p] = qy; o.z32[p] = qz; }
     if (o.perm) o.perm[p] = real ? (int32_t)idx : -1;
     // Cluster sphere: centre of the cluster's box, radius = farthest member (+ a relative
     // margin so that rounding never shrinks it).
@@ -298,7 +304,7 @@ size_t sort_scratch_bytes(int64_t n)
     const int64_t nb = sort_blocks(n > 0 ? n : 1);
     size_t b = 0;
     b += 4 * round_up(n * 4, 256);                 // keys[2], vals[2]
-    b += round_up(256 * nb * 4, 256);              // counts
+    b += 3 * round_up(256 * nb * 4, 256);          // counts of the three passes
     b += round_up(kBboxBlocks * 6 * 8, 256);       // bbox partials
     b += 256 + 256;                                // bbox, centre
     return b;
@@ -310,7 +316,8 @@ void carve_sort_scratch(void *base, int64_t n, PackScratch &ps)
     const int64_t nb = sort_blocks(n > 0 ? n : 1);
     for (int k = 0; k < 2; ++k) { ps.keys[k] = (uint32_t *)p; p += round_up(n * 4, 256); }
     for (int k = 0; k < 2; ++k) { ps.vals[k] = (uint32_t *)p; p += round_up(n * 4, 256); }
-    ps.counts = (uint32_t *)p; p += round_up(256 * nb * 4, 256);
+    for (int k = 0; k < 3; ++k) { ps.counts[k] = (uint32_t *)p; p += round_up(256 * nb * 4, 256); }
+    ps.n_counts = 256 * nb;
     ps.bbox_part = (double *)p; p += round_up(kBboxBlocks * 6 * 8, 256);
     ps.bbox = (double *)p; p += 256;
     ps.centre = (double *)p;
@@ -324,26 +331,27 @@ hipError_t launch_bbox(const double *ax, const double *ay, const double *az, int
     int blocks = (int)((tot + kBboxThreads - 1) / kBboxThreads);
     blocks = blocks < 1 ? 1 : (blocks > kBboxBlocks ? kBboxBlocks : blocks);
     hipLaunchKernelGGL(k_bbox_partial, dim3(blocks), dim3(kBboxThreads), 0, st, ax, ay, az, na,
-                       bx, by, bz, nb, ps.bbox_part);
+                       bx, by, bz, nb, ps.bbox_part, ps.counts[0], ps.n_counts);
     hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kWave), 0, st, ps.bbox_part, blocks, ps.bbox,
                        ps.centre);
     return hipGetLastError();
 }
 
+// Pass p scans counts[p] and clears counts[(p + 1) % 3] (the next pass's, and after the last
+// pass the first pass's of a following sort); its scatter counts into counts[p + 1].
 hipError_t launch_sort_points(const double *x, const double *y, const double *z, int64_t n,
                               const PackScratch &ps, const uint32_t **order, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_morton, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, y, z, n,
-                       ps.bbox, ps.keys[0], ps.vals[0]);
     const int nb = sort_blocks(n);
+    hipLaunchKernelGGL(k_morton, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, y, z, n,
+                       ps.bbox, ps.keys[0], ps.vals[0], ps.counts[0], nb);
     int cur = 0;
-    for (int shift = 0; shift < 3 * kMortonBits; shift += 8) {
-        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kSortThreads), 0, st, ps.keys[cur], n, shift,
-                           ps.counts, nb);
-        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, ps.counts, (int64_t)256 * nb);
+    for (int p = 0; p < kPasses; ++p) {
+        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, ps.counts[p], (int64_t)256 * nb,
+                           ps.counts[(p + 1) % 3]);
         hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kSortThreads), 0, st, ps.keys[cur],
-                           ps.vals[cur], ps.keys[cur ^ 1], ps.vals[cur ^ 1], n, shift, ps.counts,
-                           nb);
+                           ps.vals[cur], ps.keys[cur ^ 1], ps.vals[cur ^ 1], n, p * kDigitBits,
+                           ps.counts[p], nb, p + 1 < kPasses ? ps.counts[p + 1] : nullptr);
         cur ^= 1;
     }
     *order = ps.vals[cur];

@@ -1,36 +1,34 @@
-// sl_pair.hip -- the O(N_t N_s) pair kernels of the regularized single layer (Sec. 3.4,
+// sl_pair.hip -- the O(N_t N_s) pair kernel of the regularized single layer (Sec. 3.4,
 // eq. (regstokes)) on the gfx950 vector ALUs.
 //
 // Work decomposition.  One wavefront owns a block of 64 R consecutive (spatially sorted)
-// targets, R per lane, held in registers, and sweeps one split of the source clusters.
-// Source data are wave-uniform: every lane needs the same source at the same time, so the
-// sources are read with scalar loads into scalar registers straight from L2 -- no LDS
-// staging, no barriers, and every VALU instruction takes the source as a scalar operand.
+// targets, R per lane, held in registers.  Source data are wave-uniform: every lane needs the
+// same source at the same time, so the sources are read with scalar loads into scalar
+// registers straight from L2 -- no LDS staging, no barriers, and every VALU instruction takes
+// the source as a scalar operand.
 //
-// Each (target block, source cluster) pair is classified once by the bounding spheres:
+// Each (target block, source cluster of 64) pair is classified once by the bounding spheres:
 //   far  (gap >= cut * delta_max): plain Stokeslet, 28 flops a pair, no erf/exp;
-//   near: regularized kernel in double precision.
-// Far and near clusters run in two kernels so that the far kernel -- the bulk of the work at
-// large N -- carries none of the registers of the smoothing code and keeps a high occupancy:
-//   k_tblock: per target block, bounding sphere and far threshold (read by both kernels, so
-//             both classify every cluster from the same numbers);
-//   k_far:    far clusters; FP64 path in double precision, mixed path in single precision
-//             summed per cluster and folded into a per-target two-sum (hi, lo) pair;
-//   k_near:   near clusters in double precision, added onto k_far's partial sums (same
-//             stream, so the order of the additions is fixed);
-//   k_reduce: adds the per-split partials in split order, scales by 1/(8 pi mu) and scatters
-//             to the caller's target order.
-// The FP64 far cut is 6.9 delta (s = 1 to double precision), the mixed one rho64 >= 5 (s = 1 to
-// single precision), widened to 2^-10 box sizes so that single-precision distances stay exact
-// enough.
+//   near: regularized kernel (double precision, or the mixed path's three zones).
+// The clusters of a target block are dealt out to K wavefronts ("ways") by rank: way k takes
+// the far clusters whose rank among the block's far clusters is k mod K, and likewise for the
+// near clusters.  Every way of every block then carries the same work to within one cluster
+// of each kind, whatever the geometry, and the K partial sums per target are added in a fixed
+// order afterwards, so the result is deterministic.
+//   k_tblock: per target block, bounding sphere and far threshold;
+//   k_pair:   occupancy-sized grid; every wave pulls (block, way) items off a counter;
+//   k_reduce: adds the K partials of each target in way order, scales by 1/(8 pi mu) and
+//             scatters to the caller's target order.
+// The FP64 far cut is 6.9 delta (s = 1 to double precision), the mixed one max(rho64, 5) (s = 1
+// to single precision), widened to 2^-10 box sizes so that single-precision distances stay
+// accurate enough.
 #include "sl_internal.h"
 
 namespace sl {
 
 namespace {
 
-constexpr int kMinClustersPerSplit = 4;
-constexpr int kMaxNearWays = 64;
+constexpr int kMaxWays = 64;
 
 template <int R>
 __global__ __launch_bounds__(kWave) void k_tblock(PairArgs a, TBlockRec *__restrict__ out,
@@ -78,102 +76,184 @@ __global__ __launch_bounds__(kWave) void k_tblock(PairArgs a, TBlockRec *__restr
         rec.gap_far_mixed = gap_far;
         rec.pad0 = rec.pad1 = 0.0;
         out[tb] = rec;
-        if (tb == 0) {          // work counters of k_far and k_near, which run after this kernel
-            ctr[0] = 0u;
-            ctr[1] = 0u;
+        if (tb == 0) ctr[0] = 0u;   // work counter of k_pair, which runs after this kernel
+    }
+}
+
+// Source records of the pair kernel ([np][8]: x, y, z, gx, gy, gz, 0, 0).  They arrive as
+// restrict-qualified kernel arguments: the compiler then knows that the partial-sum stores
+// never alias them and reads each record with wide scalar loads inside the work loop.
+struct Src {
+    const double *__restrict__ d;
+    const float *__restrict__ f;
+};
+
+// Per-target state of one work item.
+template <int R, bool VARD, bool MIXED>
+struct Acc {
+    double tx[R], ty[R], tz[R];
+    float tx32[R], ty32[R], tz32[R];
+    double ax[R], ay[R], az[R];          // FP64 sums (mixed: the FP64 zone)
+    float hx[R], hy[R], hz[R], lx[R], ly[R], lz[R];   // mixed: two-sum of per-cluster sums
+    DeltaC dc[VARD ? R : 1];
+    DeltaC32 dc32[VARD ? R : 1];
+};
+
+template <int R, bool VARD, bool MIXED>
+__device__ __forceinline__ void far_cluster(const Src &S, int64_t j0, Acc<R, VARD, MIXED> &A)
+{
+    if constexpr (MIXED) {
+        float px[R], py[R], pz[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
+#pragma unroll 8
+        for (int j = 0; j < kCluster; ++j) {
+            const float *q = S.f + (j0 + j) * 8;
+            const float sx = q[0], sy = q[1], sz = q[2], gx = q[3], gy = q[4], gz = q[5];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                far_pair32(A.tx32[r], A.ty32[r], A.tz32[r], sx, sy, sz, gx, gy, gz, px[r], py[r], pz[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            two_sum_acc(px[r], A.hx[r], A.lx[r]);
+            two_sum_acc(py[r], A.hy[r], A.ly[r]);
+            two_sum_acc(pz[r], A.hz[r], A.lz[r]);
+        }
+    } else {
+#pragma unroll 4
+        for (int j = 0; j < kCluster; ++j) {
+            const double *q = S.d + (j0 + j) * 8;
+            const double sx = q[0], sy = q[1], sz = q[2], gx = q[3], gy = q[4], gz = q[5];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                far_pair64(A.tx[r], A.ty[r], A.tz[r], sx, sy, sz, gx, gy, gz, A.ax[r], A.ay[r], A.az[r]);
         }
     }
 }
 
-// Far clusters of source split `split` against target block `tb`.  The source arrays arrive as
-// separate restrict-qualified kernel arguments: the compiler then knows that the partial-sum
-// stores never alias them and keeps reading them with scalar loads inside the work loop.
-template <int R, bool MIXED>
-__device__ __forceinline__ void far_item(const PairArgs &a, const TBlockRec *__restrict__ tbr,
-                                         const double *__restrict__ Sx, const double *__restrict__ Sy,
-                                         const double *__restrict__ Sz, const double *__restrict__ Gx,
-                                         const double *__restrict__ Gy, const double *__restrict__ Gz,
-                                         const float *__restrict__ Sx32, const float *__restrict__ Sy32,
-                                         const float *__restrict__ Sz32, const float *__restrict__ Gx32,
-                                         const float *__restrict__ Gy32, const float *__restrict__ Gz32,
-                                         const double4 *__restrict__ sphere, double *__restrict__ part,
-                                         int tb, int split)
+// FP64 path: every pair in double precision.  Mixed path: near_pair_mixed (double precision
+// only below rho64 delta); single-precision terms are summed per cluster and folded into the
+// two-sum pair, as for far clusters.
+template <int R, bool VARD, bool MIXED>
+__device__ __forceinline__ void near_cluster(const Src &S, int64_t j0, const DeltaC &dcu,
+                                             const DeltaC32 &dcu32, Acc<R, VARD, MIXED> &A)
 {
+    if constexpr (MIXED) {
+        float px[R], py[R], pz[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
+#pragma unroll 4
+        for (int j = 0; j < kCluster; ++j) {
+            const float *q = S.f + (j0 + j) * 8;
+            const float sx32 = q[0], sy32 = q[1], sz32 = q[2], gx32 = q[3], gy32 = q[4], gz32 = q[5];
+            const double *e = S.d + (j0 + j) * 8;
+            const double sx = e[0], sy = e[1], sz = e[2], gx = e[3], gy = e[4], gz = e[5];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                near_pair_mixed(A.tx32[r], A.ty32[r], A.tz32[r], A.tx[r], A.ty[r], A.tz[r], sx32,
+                                sy32, sz32, gx32, gy32, gz32, sx, sy, sz, gx, gy, gz,
+                                VARD ? A.dc[VARD ? r : 0] : dcu, VARD ? A.dc32[VARD ? r : 0] : dcu32,
+                                px[r], py[r], pz[r], A.ax[r], A.ay[r], A.az[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            two_sum_acc(px[r], A.hx[r], A.lx[r]);
+            two_sum_acc(py[r], A.hy[r], A.ly[r]);
+            two_sum_acc(pz[r], A.hz[r], A.lz[r]);
+        }
+    } else {
+        DeltaC dcr[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) dcr[r] = VARD ? A.dc[VARD ? r : 0] : dcu;
+#pragma unroll 2
+        for (int j = 0; j < kCluster; ++j) {
+            const double *q = S.d + (j0 + j) * 8;
+            const double sx = q[0], sy = q[1], sz = q[2], gx = q[3], gy = q[4], gz = q[5];
+            near_pairs64<R>(A.tx, A.ty, A.tz, sx, sy, sz, gx, gy, gz, dcr, A.ax, A.ay, A.az);
+        }
+    }
+}
+
+// Lanes below this one whose bit is set in `mask`.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Work item (target block tb, way k).  The block's clusters are scanned 64 at a time, one per
+// lane; the ways' shares are picked by rank with ballots, and this way's clusters are processed
+// in ascending cluster order.
+template <int R, bool VARD, bool MIXED>
+__device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec *__restrict__ tbr,
+                                          const Src &S, const double4 *__restrict__ sphere,
+                                          double *__restrict__ part, int tb, int k)
+{
+    const uint32_t K = (uint32_t)a.n_ways;
     const int lane = threadIdx.x;
     const int64_t t0 = (int64_t)tb * (kWave * R);
     const int64_t np_t = a.t.np;
     const TBlockRec rec = tbr[tb];
 
-    double tx[R], ty[R], tz[R];
-    float tx32[R], ty32[R], tz32[R];
-    double ax[R], ay[R], az[R];
-    float hx[R], hy[R], hz[R], lx[R], ly[R], lz[R];
+    Acc<R, VARD, MIXED> A;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t i = t0 + r * kWave + lane;
-        if constexpr (MIXED) {
-            tx32[r] = a.t.x32[i];
-            ty32[r] = a.t.y32[i];
-            tz32[r] = a.t.z32[i];
-            hx[r] = hy[r] = hz[r] = lx[r] = ly[r] = lz[r] = 0.0f;
-        } else {
-            tx[r] = a.t.x[i];
-            ty[r] = a.t.y[i];
-            tz[r] = a.t.z[i];
-            ax[r] = ay[r] = az[r] = 0.0;
+        A.tx[r] = a.t.x[i];
+        A.ty[r] = a.t.y[i];
+        A.tz[r] = a.t.z[i];
+        if constexpr (VARD) {
+            A.dc[VARD ? r : 0] = make_delta(a.t.delta[i]);
+            if constexpr (MIXED) A.dc32[VARD ? r : 0] = make_delta32(a.t.delta[i], a.rho64);
         }
+        if constexpr (MIXED) {
+            A.tx32[r] = a.t.x32[i];
+            A.ty32[r] = a.t.y32[i];
+            A.tz32[r] = a.t.z32[i];
+        }
+        A.ax[r] = A.ay[r] = A.az[r] = 0.0;
+        A.hx[r] = A.hy[r] = A.hz[r] = A.lx[r] = A.ly[r] = A.lz[r] = 0.0f;
     }
+    const DeltaC dcu = make_delta(a.delta);
+    const DeltaC32 dcu32 = make_delta32(a.delta, a.rho64);
 
     const int64_t n_cl = a.s.np / kCluster;
-    const int64_t c_begin = (int64_t)split * a.clusters_per_split;
-    const int64_t c_end = c_begin + a.clusters_per_split < n_cl ? c_begin + a.clusters_per_split : n_cl;
-    for (int64_t c = c_begin; c < c_end; ++c) {
-        if (!cluster_is_far(rec, sphere[c])) continue;
-        const int64_t j0 = c * kCluster;
-        if constexpr (MIXED) {
-            float px[R], py[R], pz[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
-#pragma unroll 8
-            for (int j = 0; j < kCluster; ++j) {
-                const float sx = Sx32[j0 + j], sy = Sy32[j0 + j], sz = Sz32[j0 + j];
-                const float gx = Gx32[j0 + j], gy = Gy32[j0 + j], gz = Gz32[j0 + j];
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                    far_pair32(tx32[r], ty32[r], tz32[r], sx, sy, sz, gx, gy, gz, px[r], py[r], pz[r]);
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                two_sum_acc(px[r], hx[r], lx[r]);
-                two_sum_acc(py[r], hy[r], ly[r]);
-                two_sum_acc(pz[r], hz[r], lz[r]);
-            }
-        } else {
-#pragma unroll 4
-            for (int j = 0; j < kCluster; ++j) {
-                const double sx = Sx[j0 + j], sy = Sy[j0 + j], sz = Sz[j0 + j];
-                const double gx = Gx[j0 + j], gy = Gy[j0 + j], gz = Gz[j0 + j];
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                    far_pair64(tx[r], ty[r], tz[r], sx, sy, sz, gx, gy, gz, ax[r], ay[r], az[r]);
-            }
+    uint32_t rank_far = 0, rank_near = 0;
+    for (int64_t c0 = 0; c0 < n_cl; c0 += kWave) {
+        const int64_t cl = c0 + lane;
+        const bool valid = cl < n_cl;
+        const bool far = valid && cluster_is_far(rec, sphere[valid ? cl : 0]);
+        const bool near = valid && !far;
+        const uint64_t mf = __builtin_amdgcn_ballot_w64(far);
+        const uint64_t mn = __builtin_amdgcn_ballot_w64(near);
+        const uint32_t rk = (far ? rank_far + lanes_below(mf) : rank_near + lanes_below(mn)) % K;
+        const uint64_t mine = __builtin_amdgcn_ballot_w64(valid && rk == (uint32_t)k);
+        rank_far += (uint32_t)__builtin_popcountll(mf);
+        rank_near += (uint32_t)__builtin_popcountll(mn);
+        uint64_t m = mine;
+        while (m) {
+            const int b = __builtin_ctzll(m);
+            m &= m - 1;
+            const int64_t j0 = (c0 + b) * kCluster;
+            if ((mf >> b) & 1) far_cluster<R, VARD, MIXED>(S, j0, A);
+            else near_cluster<R, VARD, MIXED>(S, j0, dcu, dcu32, A);
         }
     }
 
-    double *px = part + ((int64_t)split * 3 + 0) * np_t;
-    double *py = part + ((int64_t)split * 3 + 1) * np_t;
-    double *pz = part + ((int64_t)split * 3 + 2) * np_t;
+    double *px = part + ((int64_t)k * 3 + 0) * np_t;
+    double *py = part + ((int64_t)k * 3 + 1) * np_t;
+    double *pz = part + ((int64_t)k * 3 + 2) * np_t;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t i = t0 + r * kWave + lane;
         if constexpr (MIXED) {
-            px[i] = (double)hx[r] + (double)lx[r];
-            py[i] = (double)hy[r] + (double)ly[r];
-            pz[i] = (double)hz[r] + (double)lz[r];
+            px[i] = A.ax[r] + ((double)A.hx[r] + (double)A.lx[r]);
+            py[i] = A.ay[r] + ((double)A.hy[r] + (double)A.ly[r]);
+            pz[i] = A.az[r] + ((double)A.hz[r] + (double)A.lz[r]);
         } else {
-            px[i] = ax[r];
-            py[i] = ay[r];
-            pz[i] = az[r];
+            px[i] = A.ax[r];
+            py[i] = A.ay[r];
+            pz[i] = A.az[r];
         }
     }
 }
@@ -186,178 +266,48 @@ __device__ __forceinline__ uint32_t next_item(uint32_t *__restrict__ ctr)
     return __builtin_amdgcn_readfirstlane(v);
 }
 
-// Occupancy-sized grid; every wave pulls (split, target block) items until none are left.
-// Items are split-major, so the waves working at the same time share one source split in L2.
-template <int R, bool MIXED>
-__global__ __launch_bounds__(kWave) void k_far(PairArgs a, const TBlockRec *__restrict__ tbr,
-                                               const double *__restrict__ Sx, const double *__restrict__ Sy,
-                                               const double *__restrict__ Sz, const double *__restrict__ Gx,
-                                               const double *__restrict__ Gy, const double *__restrict__ Gz,
-                                               const float *__restrict__ Sx32, const float *__restrict__ Sy32,
-                                               const float *__restrict__ Sz32, const float *__restrict__ Gx32,
-                                               const float *__restrict__ Gy32, const float *__restrict__ Gz32,
-                                               const double4 *__restrict__ sphere, double *__restrict__ part,
-                                               uint32_t *__restrict__ ctr)
-{
-    const uint32_t n_items = (uint32_t)a.n_tblocks * (uint32_t)a.n_splits;
-    for (uint32_t item = next_item(ctr); item < n_items; item = next_item(ctr)) {
-        const int tb = (int)(item % (uint32_t)a.n_tblocks);
-        const int split = (int)(item / (uint32_t)a.n_tblocks);
-        far_item<R, MIXED>(a, tbr, Sx, Sy, Sz, Gx, Gy, Gz, Sx32, Sy32, Sz32, Gx32, Gy32, Gz32,
-                           sphere, part, tb, split);
-    }
-}
-
-// Near clusters of a target block are few and contiguous in the sorted order, so they are dealt
-// out by rank instead of by source range: wave (tb, k) scans all clusters 64 at a time (one per
-// lane), and takes the near clusters whose rank among the block's near clusters is k mod K.
-// FP64 path: every pair in double precision.  Mixed path: near_pair_mixed (double precision only
-// below rho64 delta); single-precision terms are summed per cluster and folded into a two-sum
-// (hi, lo) pair per target, as in the far kernel.
+// Occupancy-sized grid; every wave pulls (block, way) items until none are left.  Items are
+// block-major, so the K waves of a block run at about the same time.
 template <int R, bool VARD, bool MIXED>
-__device__ __forceinline__ void near_item(const PairArgs &a, const TBlockRec *__restrict__ tbr,
-                                          const double *__restrict__ Sx, const double *__restrict__ Sy,
-                                          const double *__restrict__ Sz, const double *__restrict__ Gx,
-                                          const double *__restrict__ Gy, const double *__restrict__ Gz,
-                                          const float *__restrict__ Sx32, const float *__restrict__ Sy32,
-                                          const float *__restrict__ Sz32, const float *__restrict__ Gx32,
-                                          const float *__restrict__ Gy32, const float *__restrict__ Gz32,
-                                          const double4 *__restrict__ sphere,
-                                          double *__restrict__ part_near, int tb, int k)
+__global__ __launch_bounds__(kWave) void k_pair(PairArgs a, const TBlockRec *__restrict__ tbr,
+                                                const double *__restrict__ Sd,
+                                                const float *__restrict__ Sf,
+                                                const double4 *__restrict__ sphere, double *__restrict__ part,
+                                                uint32_t *__restrict__ ctr)
 {
-    const int K = a.near_ways;
-    const int lane = threadIdx.x;
-    const int64_t t0 = (int64_t)tb * (kWave * R);
-    const int64_t np_t = a.t.np;
-    const TBlockRec rec = tbr[tb];
-
-    double tx[R], ty[R], tz[R], ax[R], ay[R], az[R];
-    float tx32[R], ty32[R], tz32[R], hx[R], hy[R], hz[R], lx[R], ly[R], lz[R];
-    DeltaC dcv[R];
-    DeltaC32 dcv32[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t i = t0 + r * kWave + lane;
-        tx[r] = a.t.x[i];
-        ty[r] = a.t.y[i];
-        tz[r] = a.t.z[i];
-        if constexpr (VARD) {
-            dcv[r] = make_delta(a.t.delta[i]);
-            if constexpr (MIXED) dcv32[r] = make_delta32(a.t.delta[i], a.rho64);
-        }
-        if constexpr (MIXED) {
-            tx32[r] = a.t.x32[i];
-            ty32[r] = a.t.y32[i];
-            tz32[r] = a.t.z32[i];
-        }
-        ax[r] = ay[r] = az[r] = 0.0;
-        hx[r] = hy[r] = hz[r] = lx[r] = ly[r] = lz[r] = 0.0f;
-    }
-    const DeltaC dcu = make_delta(a.delta);
-    const DeltaC32 dcu32 = make_delta32(a.delta, a.rho64);
-
-    const int64_t n_cl = a.s.np / kCluster;
-    uint32_t rank = 0;
-    for (int64_t c0 = 0; c0 < n_cl; c0 += kWave) {
-        const int64_t cl = c0 + lane;
-        const bool near = cl < n_cl && !cluster_is_far(rec, sphere[cl]);
-        uint64_t mask = __ballot(near);
-        while (mask) {
-            const int b = __builtin_ctzll(mask);
-            mask &= mask - 1;
-            if ((int)(rank++ % (uint32_t)K) != k) continue;
-            const int64_t j0 = (c0 + b) * kCluster;
-            if constexpr (MIXED) {
-                float px[R], py[R], pz[R];
-#pragma unroll
-                for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
-#pragma unroll 4
-                for (int j = 0; j < kCluster; ++j) {
-                    const float sx32 = Sx32[j0 + j], sy32 = Sy32[j0 + j], sz32 = Sz32[j0 + j];
-                    const float gx32 = Gx32[j0 + j], gy32 = Gy32[j0 + j], gz32 = Gz32[j0 + j];
-                    const double sx = Sx[j0 + j], sy = Sy[j0 + j], sz = Sz[j0 + j];
-                    const double gx = Gx[j0 + j], gy = Gy[j0 + j], gz = Gz[j0 + j];
-#pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        near_pair_mixed(tx32[r], ty32[r], tz32[r], tx[r], ty[r], tz[r], sx32, sy32,
-                                        sz32, gx32, gy32, gz32, sx, sy, sz, gx, gy, gz,
-                                        VARD ? dcv[r] : dcu, VARD ? dcv32[r] : dcu32, px[r], py[r],
-                                        pz[r], ax[r], ay[r], az[r]);
-                }
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    two_sum_acc(px[r], hx[r], lx[r]);
-                    two_sum_acc(py[r], hy[r], ly[r]);
-                    two_sum_acc(pz[r], hz[r], lz[r]);
-                }
-            } else {
-#pragma unroll 2
-                for (int j = 0; j < kCluster; ++j) {
-                    const double sx = Sx[j0 + j], sy = Sy[j0 + j], sz = Sz[j0 + j];
-                    const double gx = Gx[j0 + j], gy = Gy[j0 + j], gz = Gz[j0 + j];
-#pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        near_pair64(tx[r], ty[r], tz[r], sx, sy, sz, gx, gy, gz, VARD ? dcv[r] : dcu,
-                                    ax[r], ay[r], az[r]);
-                }
-            }
-        }
-    }
-
-    double *px = part_near + ((int64_t)k * 3 + 0) * np_t;
-    double *py = part_near + ((int64_t)k * 3 + 1) * np_t;
-    double *pz = part_near + ((int64_t)k * 3 + 2) * np_t;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t i = t0 + r * kWave + lane;
-        px[i] = ax[r] + ((double)hx[r] + (double)lx[r]);
-        py[i] = ay[r] + ((double)hy[r] + (double)ly[r]);
-        pz[i] = az[r] + ((double)hz[r] + (double)lz[r]);
-    }
-}
-
-// Occupancy-sized grid pulling (target block, way) items, block-major so that the waves of one
-// block (which read the same near sources) run together.
-template <int R, bool VARD, bool MIXED>
-__global__ __launch_bounds__(kWave) void k_near(PairArgs a, const TBlockRec *__restrict__ tbr,
-                                                const double *__restrict__ Sx, const double *__restrict__ Sy,
-                                                const double *__restrict__ Sz, const double *__restrict__ Gx,
-                                                const double *__restrict__ Gy, const double *__restrict__ Gz,
-                                                const float *__restrict__ Sx32, const float *__restrict__ Sy32,
-                                                const float *__restrict__ Sz32, const float *__restrict__ Gx32,
-                                                const float *__restrict__ Gy32, const float *__restrict__ Gz32,
-                                                const double4 *__restrict__ sphere,
-                                                double *__restrict__ part_near, uint32_t *__restrict__ ctr)
-{
-    const uint32_t n_items = (uint32_t)a.n_tblocks * (uint32_t)a.near_ways;
+    const Src S{Sd, Sf};
+    const uint32_t K = (uint32_t)a.n_ways;
+    const uint32_t n_items = (uint32_t)a.n_tblocks * K;
     for (uint32_t item = next_item(ctr); item < n_items; item = next_item(ctr))
-        near_item<R, VARD, MIXED>(a, tbr, Sx, Sy, Sz, Gx, Gy, Gz, Sx32, Sy32, Sz32, Gx32, Gy32, Gz32,
-                                  sphere, part_near, (int)(item / (uint32_t)a.near_ways),
-                                  (int)(item % (uint32_t)a.near_ways));
+        pair_item<R, VARD, MIXED>(a, tbr, S, sphere, part, (int)(item / K), (int)(item % K));
 }
 
-// Per target: far partials of the source splits, then near partials of the K ways, in order.
-__global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ part, int n_splits,
-                                                const double *__restrict__ part_near, int near_ways,
+// Per target: the K way partials in way order.  A block of 4 waves serves 64 targets; wave w
+// sums ways w, w + 4, ... and wave 0 adds the four sums in order.
+__global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ part, int n_ways,
                                                 int64_t np, const int32_t *__restrict__ perm,
                                                 double scale, double *__restrict__ ux,
                                                 double *__restrict__ uy, double *__restrict__ uz)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
-    const int32_t idx = perm[p];
-    if (idx < 0) return;
+    __shared__ double sh[4][3][kWave];
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const int64_t p = (int64_t)blockIdx.x * kWave + lane;   // np is a multiple of 64
     double a = 0.0, b = 0.0, c = 0.0;
-    for (int s = 0; s < n_splits; ++s) {
+    for (int s = w; s < n_ways; s += 4) {
         a += part[((int64_t)s * 3 + 0) * np + p];
         b += part[((int64_t)s * 3 + 1) * np + p];
         c += part[((int64_t)s * 3 + 2) * np + p];
     }
-    for (int s = 0; s < near_ways; ++s) {
-        a += part_near[((int64_t)s * 3 + 0) * np + p];
-        b += part_near[((int64_t)s * 3 + 1) * np + p];
-        c += part_near[((int64_t)s * 3 + 2) * np + p];
-    }
+    sh[w][0][lane] = a;
+    sh[w][1][lane] = b;
+    sh[w][2][lane] = c;
+    __syncthreads();
+    if (w != 0) return;
+    const int32_t idx = perm[p];
+    if (idx < 0) return;
+    a = ((sh[0][0][lane] + sh[1][0][lane]) + sh[2][0][lane]) + sh[3][0][lane];
+    b = ((sh[0][1][lane] + sh[1][1][lane]) + sh[2][1][lane]) + sh[3][1][lane];
+    c = ((sh[0][2][lane] + sh[1][2][lane]) + sh[2][2][lane]) + sh[3][2][lane];
     ux[idx] = a * scale;
     uy[idx] = b * scale;
     uz[idx] = c * scale;
@@ -371,8 +321,8 @@ __global__ __launch_bounds__(256) void k_fill_zero(double *__restrict__ ux, doub
 }
 
 // Resident wavefronts per CU of a kernel (queried once per kernel instance).
-template <typename K>
-int resident_waves(K kernel)
+template <typename Kern>
+int resident_waves(Kern kernel)
 {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)kernel, kWave, 0) != hipSuccess ||
@@ -381,8 +331,8 @@ int resident_waves(K kernel)
     return nb;
 }
 
-template <typename K>
-unsigned work_grid(K kernel, int &cache, int n_cu, int64_t n_items)
+template <typename Kern>
+unsigned work_grid(Kern kernel, int &cache, int n_cu, int64_t n_items)
 {
     if (cache == 0) cache = resident_waves(kernel);
     const int64_t g = (int64_t)n_cu * cache;
@@ -393,41 +343,30 @@ template <int R>
 hipError_t launch_r(const PairArgs &a, const PairPlan &p, bool mixed, bool vard, hipStream_t st,
                     const PairTiming *tm)
 {
-    static int occ_far[2] = {0, 0}, occ_near[4] = {0, 0, 0, 0};
+    static int occ[4] = {0, 0, 0, 0};
     TBlockRec *rec = reinterpret_cast<TBlockRec *>(a.tblock_scratch);
     uint32_t *ctr = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(a.tblock_scratch) +
                                                  tblock_scratch_bytes(p.n_tblocks) - 256);
     const SrcView &s = a.s;
     hipLaunchKernelGGL((k_tblock<R>), dim3(p.n_tblocks), dim3(kWave), 0, st, a, rec, (int)mixed, ctr);
     if (tm && tm->e0) (void)hipEventRecord(tm->e0, st);
-    const int64_t n_far = (int64_t)p.n_tblocks * p.n_splits;
-    if (mixed)
-        hipLaunchKernelGGL((k_far<R, true>), dim3(work_grid(k_far<R, true>, occ_far[1], p.n_cu, n_far)),
-                           dim3(kWave), 0, st, a, rec, s.x, s.y, s.z, s.gx, s.gy, s.gz, s.x32, s.y32,
-                           s.z32, s.gx32, s.gy32, s.gz32, s.sphere, a.part, ctr);
-    else
-        hipLaunchKernelGGL((k_far<R, false>), dim3(work_grid(k_far<R, false>, occ_far[0], p.n_cu, n_far)),
-                           dim3(kWave), 0, st, a, rec, s.x, s.y, s.z, s.gx, s.gy, s.gz, s.x32, s.y32,
-                           s.z32, s.gx32, s.gy32, s.gz32, s.sphere, a.part, ctr);
-    if (tm && tm->e1) (void)hipEventRecord(tm->e1, st);
-    const int64_t n_near = (int64_t)p.n_tblocks * p.near_ways;
-#define SL_NEAR_LAUNCH(V, M, SLOT)                                                                  \
-    hipLaunchKernelGGL((k_near<R, V, M>), dim3(work_grid(k_near<R, V, M>, occ_near[SLOT], p.n_cu, n_near)), \
-                       dim3(kWave), 0, st, a, rec, s.x, s.y, s.z, s.gx, s.gy, s.gz, s.x32, s.y32, s.z32, \
-                       s.gx32, s.gy32, s.gz32, s.sphere, a.part_near, ctr + 1)
+    const int64_t n_items = (int64_t)p.n_tblocks * p.n_ways;
+#define SL_PAIR_LAUNCH(V, M, SLOT)                                                                  \
+    hipLaunchKernelGGL((k_pair<R, V, M>), dim3(work_grid(k_pair<R, V, M>, occ[SLOT], p.n_cu, n_items)), \
+                       dim3(kWave), 0, st, a, rec, s.d, s.f32, s.sphere, a.part, ctr)
     if (vard) {
-        if (mixed) SL_NEAR_LAUNCH(true, true, 3); else SL_NEAR_LAUNCH(true, false, 1);
+        if (mixed) SL_PAIR_LAUNCH(true, true, 3); else SL_PAIR_LAUNCH(true, false, 1);
     } else {
-        if (mixed) SL_NEAR_LAUNCH(false, true, 2); else SL_NEAR_LAUNCH(false, false, 0);
+        if (mixed) SL_PAIR_LAUNCH(false, true, 2); else SL_PAIR_LAUNCH(false, false, 0);
     }
-#undef SL_NEAR_LAUNCH
-    if (tm && tm->e2) (void)hipEventRecord(tm->e2, st);
+#undef SL_PAIR_LAUNCH
+    if (tm && tm->e1) (void)hipEventRecord(tm->e1, st);
     return hipGetLastError();
 }
 
 }  // namespace
 
-// Target-block records followed by 256 bytes holding the two work counters.
+// Target-block records followed by 256 bytes holding the work counter.
 size_t tblock_scratch_bytes(int n_tblocks) { return (size_t)n_tblocks * sizeof(TBlockRec) + 256; }
 
 PairPlan plan_pairs(int64_t np_src, int64_t np_tgt, int R, int waves_wanted)
@@ -436,15 +375,11 @@ PairPlan plan_pairs(int64_t np_src, int64_t np_tgt, int R, int waves_wanted)
     p.R = R;
     p.n_tblocks = (int)(np_tgt / (kWave * R));
     const int64_t n_cl = np_src / kCluster;
-    int64_t S = (waves_wanted + p.n_tblocks - 1) / p.n_tblocks;
-    const int64_t smax = n_cl / kMinClustersPerSplit > 0 ? n_cl / kMinClustersPerSplit : 1;
-    S = S < 1 ? 1 : (S > smax ? smax : S);
-    p.clusters_per_split = (n_cl + S - 1) / S;
-    p.n_splits = (int)((n_cl + p.clusters_per_split - 1) / p.clusters_per_split);
     int64_t K = (waves_wanted + p.n_tblocks - 1) / p.n_tblocks;
-    K = K < 1 ? 1 : (K > kMaxNearWays ? kMaxNearWays : K);
+    K = K < 1 ? 1 : (K > kMaxWays ? kMaxWays : K);
     K = K > n_cl ? n_cl : K;
-    p.near_ways = (int)K;
+    p.n_ways = (int)K;
+    p.n_cu = 0;
     return p;
 }
 
@@ -459,12 +394,11 @@ hipError_t launch_pair(const PairArgs &a, const PairPlan &p, bool mixed, bool va
     }
 }
 
-hipError_t launch_reduce(const double *part, int n_splits, const double *part_near, int near_ways,
-                         int64_t np, const int32_t *perm, double scale, double *ux, double *uy,
-                         double *uz, hipStream_t st)
+hipError_t launch_reduce(const double *part, int n_ways, int64_t np, const int32_t *perm,
+                         double scale, double *ux, double *uy, double *uz, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, part,
-                       n_splits, part_near, near_ways, np, perm, scale, ux, uy, uz);
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)(np / kWave)), dim3(256), 0, st, part, n_ways, np,
+                       perm, scale, ux, uy, uz);
     return hipGetLastError();
 }
 

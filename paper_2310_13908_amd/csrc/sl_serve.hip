@@ -853,8 +853,8 @@ sl_status get_server(sl_ctx *ctx, Server **out)
 {
     std::lock_guard<std::mutex> l(ctx->mu);
     if (!ctx->server) {
+        if (hipSetDevice(ctx->device) != hipSuccess) return fail(SL_EHIP, "serving: hipSetDevice failed");
         Server *s = new Server();
-        hipSetDevice(ctx->device);
         const sl_status st = s->init(ctx);
         if (st != SL_OK) {
             s->shutdown();
@@ -887,7 +887,7 @@ void sl_destroy(sl_ctx *ctx)
         ctx->server = nullptr;
     }
     for (auto &ev : ctx->timed)
-        for (hipEvent_t e : {ev.e0, ev.e1, ev.e2}) (void)hipEventDestroy(e);
+        for (hipEvent_t e : {ev.e0, ev.e1}) (void)hipEventDestroy(e);
     for (auto ev : ctx->spare_events) (void)hipEventDestroy(ev);
     delete ctx;
 }

@@ -236,69 +236,105 @@ def serving_leg(P, dev, log, check_oracle=True):
     return out
 
 
-def memory_leg(P, dev, log, n_large=4, n_small=124):
+def memory_leg(P, dev, log, n_large=2, n_small=62, passes=2):
     """A scaled sample of the memory-admitted stream: n_large capsules of N = 6 * 512^2
-    interleaved with n_small ones (n log-uniform in [16, 64]), RBC and ellipsoid.  The client
-    registers each surface as its request arrives, submits, and releases surfaces once their
-    request is done; when registration is refused for lack of memory it first retires the
-    oldest request.  Run with the full budget and with one of about two large surfaces."""
+    interleaved with n_small ones (n log-uniform in [16, 64]), RBC and ellipsoid, evaluated in
+    `passes` passes with a fresh density each time.  The client keeps surfaces resident across
+    passes (least recently used first out): when a registration is refused for lack of memory it
+    releases idle surfaces, else retires its oldest request first.  Run with the full budget
+    (everything stays resident) and with a budget that holds one large capsule but not two (the
+    large surfaces are evicted and registered again)."""
     import collections
     import numpy as np
     import torch
+    from capsule_inputs import forces as FO
     from capsule_inputs import workloads as W
     stream = W.memory_admitted_stream(n_large=n_large, n_small=n_small)
     t0 = time.perf_counter()
     probs = [r.problem() for r in stream.requests]
-    log(f"[bench] memory stream: {len(probs)} requests generated in {time.perf_counter() - t0:.1f} s")
-    total = float(sum(p.N * p.N for p in probs))
+    # pass k > 0 uses a fresh seeded density on the same surface
+    dens = [[p.f] + [FO.sh_force(p.surface.x0, W.SEED_C5 * 100 + 7 * k + i)
+                     for k in range(1, passes)] for i, p in enumerate(probs)]
+    log(f"[bench] memory stream: {len(probs)} capsules x {passes} passes generated in "
+        f"{time.perf_counter() - t0:.1f} s")
+    total = float(sum(p.N * p.N for p in probs)) * passes
     n_big = max(p.N for p in probs)
     per_point = 85                       # resident surface (49 B) + mixed staging (36 B) per point
-    budgets = {"full": 16 << 30, "two_large": int(2.5 * per_point * n_big)}
-    out = {"workload": f"{n_large} capsules N = {n_big} + {n_small} with n in [16, 64] "
-                       "(RBC / ellipsoid), SH density, delta = 2h; surfaces registered on "
-                       "arrival and released after their request",
-           "total_pairs": total, "requests": len(probs)}
+    budgets = {"full": 16 << 30, "one_large": int(1.15 * per_point * n_big)}
+    out = {"workload": f"{n_large} capsules N = {n_big} + {n_small} with n in [16, 64] (RBC / "
+                       f"ellipsoid), SH density, delta = 2h, {passes} passes with fresh densities; "
+                       "surfaces kept resident, least recently used released when memory is short",
+           "total_pairs": total, "requests": len(probs) * passes}
     for bname, budget in budgets.items():
         for prec in ("mixed", "fp64"):
             with P.Context(0, hbm_budget_bytes=budget) as ctx:
                 torch.cuda.synchronize()
-                live = collections.deque()
-                refused = 0
+                cur = torch.cuda.current_stream()
+                resident = collections.OrderedDict()      # capsule -> handle, LRU order
+                inflight = collections.deque()            # (rid, capsule, keep-alive)
+                busy = collections.Counter()
+                registrations = evictions = 0
                 peak = 0
+
+                def retire_done():
+                    while inflight and ctx.poll(inflight[0][0]):
+                        busy[inflight.popleft()[1]] -= 1
+
+                def make_room(nbytes, keep):
+                    """Release idle surfaces (least recently used first), then retire the
+                    oldest requests, until nbytes more fit the budget."""
+                    nonlocal evictions
+                    while budget - int(ctx.stats().bytes_admitted) < nbytes:
+                        idle = [c for c in resident if busy[c] == 0 and c != keep]
+                        if idle:
+                            ctx.release_surface(resident.pop(idle[0]))
+                            evictions += 1
+                        elif inflight:
+                            rid0, c0, _ = inflight.popleft()
+                            ctx.wait(rid0, 120.0)
+                            busy[c0] -= 1
+                        else:
+                            return
+
                 t0 = time.perf_counter()
-                for p in probs:
-                    X = torch.as_tensor(p.surface.X, device=dev)
-                    w = torch.as_tensor(p.surface.w, device=dev)
-                    f = torch.as_tensor(np.ascontiguousarray(p.f.T), device=dev)
-                    u = torch.empty_like(f)
-                    torch.cuda.synchronize()
-                    while True:
-                        try:
-                            h = ctx.register_surface(X, w, p.delta)
-                            break
-                        except P.SlError as e:
-                            if e.status != P.SL_EBUSY or not live:
-                                raise
-                            refused += 1
-                            rid0, h0, _ = live.popleft()
-                            ctx.wait(rid0, 600.0)
-                            ctx.release_surface(h0)
-                    rid = ctx.submit_prepared(h, f, u, precision=prec)
-                    live.append((rid, h, (f, u)))
-                    peak = max(peak, int(ctx.stats().bytes_admitted))
-                    while live and ctx.poll(live[0][0]):
-                        ctx.release_surface(live.popleft()[1])
-                while live:
-                    rid0, h0, _ = live.popleft()
-                    ctx.wait(rid0, 600.0)
-                    ctx.release_surface(h0)
+                for k in range(passes):
+                    for i, p in enumerate(probs):
+                        np_i = -(-p.N // 256) * 256
+                        if i in resident:
+                            resident.move_to_end(i)
+                        else:
+                            X = torch.as_tensor(p.surface.X, device=dev)
+                            w = torch.as_tensor(p.surface.w, device=dev)
+                            cur.synchronize()    # this stream only: the serving kernel keeps running
+                            make_room(49 * np_i, None)
+                            while True:
+                                try:
+                                    resident[i] = ctx.register_surface(X, w, p.delta)
+                                    registrations += 1
+                                    break
+                                except P.SlError as e:
+                                    if e.status != P.SL_EBUSY or not (resident or inflight):
+                                        raise
+                                    make_room(budget, None)   # everything idle goes
+                        make_room((36 if prec == "mixed" else 24) * np_i, i)
+                        f = torch.as_tensor(np.ascontiguousarray(dens[i][k].T), device=dev)
+                        u = torch.empty_like(f)
+                        cur.synchronize()
+                        rid = ctx.submit_prepared(resident[i], f, u, precision=prec)
+                        inflight.append((rid, i, (f, u)))
+                        busy[i] += 1
+                        peak = max(peak, int(ctx.stats().bytes_admitted))
+                        retire_done()
+                while inflight:
+                    rid0, c0, _ = inflight.popleft()
+                    ctx.wait(rid0, 120.0)
                 dt = time.perf_counter() - t0
             out[f"{bname}_{prec}"] = {"budget_bytes": budget, "seconds": round(dt, 3),
                                       "gpair_s": round(total / dt / 1e9, 2),
-                                      "registrations_refused": refused,
+                                      "registrations": registrations, "evictions": evictions,
                                       "peak_bytes_admitted": peak}
             log(f"[bench] memory stream {bname} {prec}: {dt:.2f} s  {total / dt / 1e9:.0f} Gpair/s  "
-                f"refused {refused}  peak {peak / 2**30:.2f} GiB")
+                f"registrations {registrations} evictions {evictions}  peak {peak / 2**30:.2f} GiB")
     return out
 
 

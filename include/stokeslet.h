@@ -76,8 +76,7 @@ const char *sl_last_error(void);
  * SL_PARAM_KERNEL_TIMING: 1 = bracket every pair-kernel launch of sl_eval with HIP events on
  *   the caller's stream and accumulate the elapsed time into sl_stats; 0 (default) = off.
  * SL_PARAM_TARGETS_PER_LANE: targets each lane of the pair kernels keeps in registers
- *   (1, 2 or 4; 0 = automatic, the default: 1 in SL_MIXED, 2 in SL_FP64, 4 in SL_FP64 from
- *   2^17 targets).
+ *   (1, 2 or 4; 0 = automatic, the default: 1 in SL_MIXED, 2 in SL_FP64).
  * SL_PARAM_WAVES_PER_SIMD: granularity of the pair kernels' work items: the sources are split
  *   until there are about this many items per SIMD (1..32; default 16). */
 typedef enum {
@@ -120,8 +119,9 @@ sl_status sl_eval(sl_ctx *ctx, sl_precision prec,
  *
  * sl_surface_register copies n nodes (x, y, z, w: device arrays) into library-owned HBM,
  * sorts them spatially once and keeps them resident; targets are the nodes themselves and
- * delta is fixed per surface.  It is synchronous.  Admission: SL_EBUSY if the surface's
- * footprint does not fit the remaining budget.
+ * delta is fixed per surface.  It is synchronous: when the serving kernel is busy it lets the
+ * queued work finish first.  Admission: SL_EBUSY if the surface's footprint does not fit the
+ * remaining budget, or if submitted requests are still waiting for memory.
  *
  * sl_surface_release drops the handle; its memory is returned once no submitted request on
  * it is still in flight.
@@ -131,7 +131,9 @@ sl_status sl_eval(sl_ctx *ctx, sl_precision prec,
  * The request's work (one item per block of targets) joins the queue of a single persistent
  * kernel that serves every in-flight request; requests submitted while others run are
  * interleaved with them on the device.  Each request's result is bit-identical to the same
- * request served alone.  Admission: SL_EBUSY if the request's staging memory does not fit.
+ * request served alone.  A request is admitted at once when its staging memory fits the
+ * budget, otherwise it waits (first in, first out) until memory is returned; SL_EBUSY only if
+ * its staging exceeds the whole budget.
  * Thread-safe.
  *
  * sl_poll sets *done to 1 when the request's output is complete and visible to later stream

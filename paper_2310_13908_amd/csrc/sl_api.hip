@@ -264,7 +264,7 @@ sl_status sl_eval(sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *s
         wps = ctx->waves_per_simd;
     }
     if (R == 0)   // measured on MI355X: the single-precision loops want occupancy, FP64 ILP
-        R = mixed ? 1 : (np_t >= ((int64_t)1 << 17) ? 4 : 2);
+        R = mixed ? 1 : 2;
     PairPlan plan = plan_pairs(np_s, np_t, R, ctx->n_cu * 4 * wps);
     plan.n_cu = ctx->n_cu;
 

@@ -106,7 +106,7 @@ __device__ __forceinline__ void far_cluster(const Src &S, int64_t j0, Acc<R, VAR
         float px[R], py[R], pz[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
-#pragma unroll 8
+#pragma unroll 4
         for (int j = 0; j < kCluster; ++j) {
             const float *q = S.f + (j0 + j) * 8;
             const float sx = q[0], sy = q[1], sz = q[2], gx = q[3], gy = q[4], gz = q[5];
@@ -143,7 +143,7 @@ __device__ __forceinline__ void near_cluster(const Src &S, int64_t j0, const Del
         float px[R], py[R], pz[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
-#pragma unroll 4
+#pragma unroll 1
         for (int j = 0; j < kCluster; ++j) {
             const float *q = S.f + (j0 + j) * 8;
             const float sx32 = q[0], sy32 = q[1], sz32 = q[2], gx32 = q[3], gy32 = q[4], gz32 = q[5];

@@ -335,11 +335,14 @@ __global__ __launch_bounds__(kWave) void k_serve(ServeArgs a)
         // The first wave of this launch starts the idle clock; later-starting waves must not
         // push it forward, or the kernel would outlive its idle limit.
         uint64_t seen = __hip_atomic_load(&a.dc->launch_seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // It also clears the stop mirror left by a drain of the previous launch.
         if (seen != a.launch_id &&
             __hip_atomic_compare_exchange_strong(&a.dc->launch_seen, &seen, a.launch_id, __ATOMIC_RELAXED,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            __hip_atomic_store(&a.dc->stop_mirror, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_max(&a.dc->last_activity, (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
     int rounds = 0;
     for (;;) {
@@ -586,6 +589,7 @@ struct Server {
     hipEvent_t kdone = nullptr;
     double clock_hz = 100e6;             // rate of the device's constant wall clock
     bool kernel_launched = false;
+    int registering = 0;                 // registrations in progress: no kernel relaunch meanwhile
 
     ServeCtl *ctl = nullptr;
     WorkItem *ring = nullptr;
@@ -779,7 +783,7 @@ sl_status Server::ensure_kernel_locked()
     // (Re)launch only when published items may be unclaimed and no kernel is running.  The
     // claim mirror is a lower bound, so at worst this starts a kernel that idles out.
     const uint64_t claimed = __atomic_load_n(&ctl->claimed, __ATOMIC_ACQUIRE);
-    if (claimed >= tail) return SL_OK;
+    if (claimed >= tail || registering > 0) return SL_OK;
     if (kernel_launched) {
         const hipError_t q = hipEventQuery(kdone);
         if (q == hipErrorNotReady) return SL_OK;          // still running
@@ -908,11 +912,39 @@ sl_status sl_surface_register(sl_ctx *ctx, int64_t n, const double *x, const dou
     sf.n = n;
     sf.np = np;
     sf.delta = delta;
+    bool drain = false;
     {
         std::lock_guard<std::mutex> l(s->mu);
+        // Requests waiting for memory go first: a surface does not overtake them.
+        if (!s->pending.empty())
+            return fail(SL_EBUSY, "sl_surface_register: requests are waiting for memory");
         sf.mem = s->arena.alloc(surface_bytes(np));
         if (!sf.mem)
             return fail(SL_EBUSY, "sl_surface_register: surface does not fit the HBM budget");
+        // The persistent kernel holds every wave slot, so the packing kernels below could only
+        // start once it idles out.  Ask it to exit as soon as the queued work is done instead, and
+        // keep it from being relaunched until the surface is packed.
+        s->registering += 1;
+        if (s->kernel_launched && hipEventQuery(s->kdone) == hipErrorNotReady) {
+            __atomic_store_n(&s->ctl->stop, 1ull, __ATOMIC_RELEASE);
+            drain = true;
+        }
+    }
+    auto done_registering = [&]() {
+        std::lock_guard<std::mutex> l(s->mu);
+        if (--s->registering == 0) __atomic_store_n(&s->ctl->stop, 0ull, __ATOMIC_RELEASE);
+        s->cv.notify_all();
+    };
+    if (drain) {
+        const hipError_t ed = hipEventSynchronize(s->kdone);
+        if (ed != hipSuccess) {
+            {
+                std::lock_guard<std::mutex> l(s->mu);
+                s->arena.release(sf.mem);
+            }
+            done_registering();
+            return hip_fail(ed, "sl_surface_register: waiting for the serving kernel");
+        }
     }
     char *p = sf.mem;
     auto take = [&](int64_t bytes) { char *q = p; p += round_up(bytes, 256); return q; };
@@ -943,6 +975,7 @@ sl_status sl_surface_register(sl_ctx *ctx, int64_t n, const double *x, const dou
     if (scratch) (void)hipFreeAsync(scratch, s->aux);
     const hipError_t es = hipStreamSynchronize(s->aux);
     if (e == hipSuccess) e = es;
+    done_registering();
     std::lock_guard<std::mutex> l(s->mu);
     if (e != hipSuccess) {
         s->arena.release(sf.mem);
@@ -1007,6 +1040,9 @@ sl_status sl_submit(sl_ctx *ctx, uint64_t handle, sl_precision prec, const doubl
     sf.refs += 1;
     s->reqs[r.id] = r;
     s->pending.push_back(r.id);
+    // Admit now when the memory is there, so that the request holds its staging from this call
+    // on (a later registration cannot take it).
+    s->admit_locked();
     *request = r.id;
     s->cv.notify_all();
     return SL_OK;

@@ -149,3 +149,19 @@ def test_kernel_relaunch_after_idle(ctx, surfaces, refs):
     u = ctx.wait(rid).cpu().numpy()
     assert eps(u, refs[0]) < TOL["mixed"]
     assert ctx.stats().kernel_launches >= n0 + 1
+
+
+def test_register_while_kernel_busy(ctx, surfaces, refs):
+    """Registering a surface while requests run drains the persistent kernel, packs the surface
+    and relaunches: the requests queued before and after the registration all complete and
+    match the oracle."""
+    (s0, f0, d0), (s2, f2, d2) = surfaces[2], surfaces[1]
+    h0 = ctx.register_surface(dev_t(s0.X), dev_t(s0.w), d0)
+    rids = [ctx.submit(h0, dev_t(f0), mu=0.8, precision="fp64")[0] for _ in range(4)]
+    n0 = ctx.stats().kernel_launches
+    h2 = ctx.register_surface(dev_t(s2.X), dev_t(s2.w), d2)   # while the requests above run
+    rid2, _ = ctx.submit(h2, dev_t(f2), mu=0.8, precision="fp64")
+    for rid in rids:
+        assert eps(ctx.wait(rid, 60.0).cpu().numpy(), refs[2]) < TOL["fp64"]
+    assert eps(ctx.wait(rid2, 60.0).cpu().numpy(), refs[1]) < TOL["fp64"]
+    assert ctx.stats().kernel_launches >= n0

@@ -4,19 +4,21 @@
 // Work decomposition.  One wavefront owns a block of 64 R consecutive (spatially sorted)
 // targets, R per lane, held in registers.  Source data are wave-uniform: every lane needs the
 // same source at the same time, so the sources are read with scalar loads into scalar
-// registers straight from L2 -- no LDS staging, no barriers, and every VALU instruction takes
-// the source as a scalar operand.
+// registers -- no LDS staging, and every VALU instruction takes the source as a scalar operand.
+// The G waves of a workgroup (mixed path) own G adjacent target blocks and walk the same source
+// clusters, so a source record fetched into the scalar cache by one of them serves the others.
 //
-// Each (target block, source cluster of 64) pair is classified once by the bounding spheres:
+// Each (target group, source cluster of 64) pair is classified once by the bounding spheres:
 //   far  (gap >= cut * delta_max): plain Stokeslet, 28 flops a pair, no erf/exp;
-//   near: regularized kernel (double precision, or the mixed path's three zones).
-// The clusters of a target block are dealt out to K wavefronts ("ways") by rank: way k takes
-// the far clusters whose rank among the block's far clusters is k mod K, and likewise for the
-// near clusters.  Every way of every block then carries the same work to within one cluster
-// of each kind, whatever the geometry, and the K partial sums per target are added in a fixed
-// order afterwards, so the result is deterministic.
-//   k_tblock: per target block, bounding sphere and far threshold;
-//   k_pair:   occupancy-sized grid; every wave pulls (block, way) items off a counter;
+//   near: regularized kernel (double precision, or the mixed path's three zones), with the
+//         smoothing evaluated only where some lane of the wavefront needs it.
+// The clusters of a group are dealt out to K ways by rank: way k takes the far clusters whose
+// rank among the group's far clusters is k mod K, and likewise for the near clusters.  Every
+// way of every group then carries the same work to within one cluster of each kind, whatever
+// the geometry, and the K partial sums per target are added in a fixed order afterwards, so the
+// result is deterministic.
+//   k_tblock: per target group, bounding sphere and far threshold;
+//   k_pair:   occupancy-sized grid; every workgroup pulls (group, way) items off a counter;
 //   k_reduce: adds the K partials of each target in way order, scales by 1/(8 pi mu) and
 //             scatters to the caller's target order.
 // The FP64 far cut is 6.9 delta (s = 1 to double precision), the mixed one max(rho64, 5) (s = 1
@@ -30,53 +32,75 @@ namespace {
 
 constexpr int kMaxWays = 64;
 
-template <int R>
+// Bounding sphere (centre of the box, farthest member, relative margin 2^-40) of the sorted
+// targets [t0, t1), computed by one wave.
+__device__ __forceinline__ void target_sphere(const PairArgs &a, int64_t t0, int64_t t1, double &cx,
+                                              double &cy, double &cz, double &rad, double &dmax)
+{
+    const int lane = threadIdx.x % kWave;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    dmax = a.delta;
+    bool first = true;
+    for (int64_t i = t0 + lane; i < t1; i += kWave) {
+        const double x = a.t.x[i], y = a.t.y[i], z = a.t.z[i];
+        if (a.t.delta) dmax = first ? a.t.delta[i] : fmax(dmax, a.t.delta[i]);
+        first = false;
+        lo[0] = fmin(lo[0], x); hi[0] = fmax(hi[0], x);
+        lo[1] = fmin(lo[1], y); hi[1] = fmax(hi[1], y);
+        lo[2] = fmin(lo[2], z); hi[2] = fmax(hi[2], z);
+    }
+    cx = 0.5 * (wave_min(lo[0]) + wave_max(hi[0]));
+    cy = 0.5 * (wave_min(lo[1]) + wave_max(hi[1]));
+    cz = 0.5 * (wave_min(lo[2]) + wave_max(hi[2]));
+    double rr = 0.0;
+    for (int64_t i = t0 + lane; i < t1; i += kWave) {
+        const double dx = a.t.x[i] - cx, dy = a.t.y[i] - cy, dz = a.t.z[i] - cz;
+        rr = fmax(rr, fma(dx, dx, fma(dy, dy, __dmul_rn(dz, dz))));
+    }
+    rad = sqrt(wave_max(rr)) * (1.0 + 0x1p-40);
+    dmax = wave_max(dmax);
+}
+
+__device__ __forceinline__ TBlockRec make_rec(const PairArgs &a, int mixed, double cx, double cy,
+                                              double cz, double rad, double dmax)
+{
+    double gap_far = a.far_cut * dmax;
+    if (mixed) {
+        const double bx = a.bbox[3] - a.bbox[0], by = a.bbox[4] - a.bbox[1], bz = a.bbox[5] - a.bbox[2];
+        gap_far = fmax(gap_far, 0x1p-10 * sqrt(fma(bx, bx, fma(by, by, __dmul_rn(bz, bz)))));
+    }
+    TBlockRec rec;
+    rec.cx = cx; rec.cy = cy; rec.cz = cz;
+    rec.rad = rad;
+    rec.gap_far = gap_far;
+    rec.gap_far_mixed = gap_far;
+    rec.pad0 = rec.pad1 = 0.0;
+    return rec;
+}
+
+// Sphere and far threshold of each group of G target blocks (G * 64 R consecutive sorted
+// targets; the last group may be short) and of each of its blocks.  Records: [n_groups] group
+// records, then [n_tblocks] block records.
+template <int R, int G>
 __global__ __launch_bounds__(kWave) void k_tblock(PairArgs a, TBlockRec *__restrict__ out,
                                                   int mixed, uint32_t *__restrict__ ctr)
 {
-    const int tb = blockIdx.x;
-    const int lane = threadIdx.x;
-    const int64_t t0 = (int64_t)tb * (kWave * R);
-    double x[R], y[R], z[R];
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    double dmax = a.delta;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t i = t0 + r * kWave + lane;
-        x[r] = a.t.x[i];
-        y[r] = a.t.y[i];
-        z[r] = a.t.z[i];
-        if (a.t.delta) dmax = r == 0 ? a.t.delta[i] : fmax(dmax, a.t.delta[i]);
-        lo[0] = fmin(lo[0], x[r]); hi[0] = fmax(hi[0], x[r]);
-        lo[1] = fmin(lo[1], y[r]); hi[1] = fmax(hi[1], y[r]);
-        lo[2] = fmin(lo[2], z[r]); hi[2] = fmax(hi[2], z[r]);
+    const int g = blockIdx.x;
+    const int n_groups = (a.n_tblocks + G - 1) / G;
+    const int64_t blk = (int64_t)kWave * R;
+    const int64_t np_t = a.t.np;
+    const int64_t t0 = (int64_t)g * G * blk;
+    const int64_t t1 = t0 + G * blk < np_t ? t0 + G * blk : np_t;
+    double cx, cy, cz, rad, dmax;
+    target_sphere(a, t0, t1, cx, cy, cz, rad, dmax);
+    if (threadIdx.x == 0) {
+        out[g] = make_rec(a, mixed, cx, cy, cz, rad, dmax);
+        if (g == 0) ctr[0] = 0u;   // work counter of k_pair, which runs after this kernel
     }
-    const double cx = 0.5 * (wave_min(lo[0]) + wave_max(hi[0]));
-    const double cy = 0.5 * (wave_min(lo[1]) + wave_max(hi[1]));
-    const double cz = 0.5 * (wave_min(lo[2]) + wave_max(hi[2]));
-    double rr = 0.0;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const double dx = x[r] - cx, dy = y[r] - cy, dz = z[r] - cz;
-        rr = fmax(rr, fma(dx, dx, fma(dy, dy, __dmul_rn(dz, dz))));
-    }
-    rr = wave_max(rr);
-    dmax = wave_max(dmax);
-    if (lane == 0) {
-        double gap_far = a.far_cut * dmax;
-        if (mixed) {
-            const double bx = a.bbox[3] - a.bbox[0], by = a.bbox[4] - a.bbox[1],
-                         bz = a.bbox[5] - a.bbox[2];
-            gap_far = fmax(gap_far, 0x1p-10 * sqrt(fma(bx, bx, fma(by, by, __dmul_rn(bz, bz)))));
-        }
-        TBlockRec rec;
-        rec.cx = cx; rec.cy = cy; rec.cz = cz;
-        rec.rad = sqrt(rr) * (1.0 + 0x1p-40);
-        rec.gap_far = gap_far;
-        rec.gap_far_mixed = gap_far;
-        rec.pad0 = rec.pad1 = 0.0;
-        out[tb] = rec;
-        if (tb == 0) ctr[0] = 0u;   // work counter of k_pair, which runs after this kernel
+    if (G == 1) return;
+    for (int b = 0; b < G && t0 + b * blk < np_t; ++b) {
+        target_sphere(a, t0 + b * blk, t0 + (b + 1) * blk, cx, cy, cz, rad, dmax);
+        if (threadIdx.x == 0) out[n_groups + g * G + b] = make_rec(a, mixed, cx, cy, cz, rad, dmax);
     }
 }
 
@@ -181,19 +205,21 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Work item (target block tb, way k).  The block's clusters are scanned 64 at a time, one per
-// lane; the ways' shares are picked by rank with ballots, and this way's clusters are processed
-// in ascending cluster order.
+// Work item (target block tb, way k).  The clusters are classified against the sphere `rec` of
+// the block's group, scanned 64 at a time, one per lane; the ways' shares are picked by rank with
+// ballots, and this way's clusters are processed in ascending cluster order.  Every wave of a
+// group walks the same clusters, so the group's waves share each source record in the scalar
+// cache.
 template <int R, bool VARD, bool MIXED>
-__device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec *__restrict__ tbr,
-                                          const Src &S, const double4 *__restrict__ sphere,
+__device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec &rec,
+                                          const TBlockRec &own, bool grouped, const Src &S,
+                                          const double4 *__restrict__ sphere,
                                           double *__restrict__ part, int tb, int k)
 {
     const uint32_t K = (uint32_t)a.n_ways;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x % kWave;
     const int64_t t0 = (int64_t)tb * (kWave * R);
     const int64_t np_t = a.t.np;
-    const TBlockRec rec = tbr[tb];
 
     Acc<R, VARD, MIXED> A;
 #pragma unroll
@@ -235,8 +261,11 @@ __device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec *__
             const int b = __builtin_ctzll(m);
             m &= m - 1;
             const int64_t j0 = (c0 + b) * kCluster;
-            if ((mf >> b) & 1) far_cluster<R, VARD, MIXED>(S, j0, A);
-            else near_cluster<R, VARD, MIXED>(S, j0, dcu, dcu32, A);
+            // near for the group, yet possibly far for this wave's own block
+            if (((mf >> b) & 1) || (grouped && cluster_is_far(own, sphere[c0 + b])))
+                far_cluster<R, VARD, MIXED>(S, j0, A);
+            else
+                near_cluster<R, VARD, MIXED>(S, j0, dcu, dcu32, A);
         }
     }
 
@@ -258,28 +287,35 @@ __device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec *__
     }
 }
 
-// Next work item of a wave (lane 0 draws from the counter; the index is made wave-uniform).
-__device__ __forceinline__ uint32_t next_item(uint32_t *__restrict__ ctr)
+// Occupancy-sized grid of workgroups of G waves.  A workgroup pulls (group, way) items off the
+// counter; wave w of the workgroup takes target block G * group + w.  Items are group-major, so
+// the K ways of a group run at about the same time.
+template <int R, bool VARD, bool MIXED, int G>
+__global__ __launch_bounds__(G * kWave) void k_pair(PairArgs a, const TBlockRec *__restrict__ recs,
+                                                    const double *__restrict__ Sd,
+                                                    const float *__restrict__ Sf,
+                                                    const double4 *__restrict__ sphere,
+                                                    double *__restrict__ part,
+                                                    uint32_t *__restrict__ ctr)
 {
-    uint32_t v = 0;
-    if (threadIdx.x == 0) v = atomicAdd(ctr, 1u);
-    return __builtin_amdgcn_readfirstlane(v);
-}
-
-// Occupancy-sized grid; every wave pulls (block, way) items until none are left.  Items are
-// block-major, so the K waves of a block run at about the same time.
-template <int R, bool VARD, bool MIXED>
-__global__ __launch_bounds__(kWave) void k_pair(PairArgs a, const TBlockRec *__restrict__ tbr,
-                                                const double *__restrict__ Sd,
-                                                const float *__restrict__ Sf,
-                                                const double4 *__restrict__ sphere, double *__restrict__ part,
-                                                uint32_t *__restrict__ ctr)
-{
+    __shared__ uint32_t sh_item;
     const Src S{Sd, Sf};
     const uint32_t K = (uint32_t)a.n_ways;
-    const uint32_t n_items = (uint32_t)a.n_tblocks * K;
-    for (uint32_t item = next_item(ctr); item < n_items; item = next_item(ctr))
-        pair_item<R, VARD, MIXED>(a, tbr, S, sphere, part, (int)(item / K), (int)(item % K));
+    const int n_groups = (a.n_tblocks + G - 1) / G;
+    const uint32_t n_items = (uint32_t)n_groups * K;
+    const int w = threadIdx.x / kWave;
+    for (;;) {
+        if (threadIdx.x == 0) sh_item = atomicAdd(ctr, 1u);
+        __syncthreads();
+        const uint32_t item = sh_item;
+        __syncthreads();
+        if (item >= n_items) break;
+        const int g = (int)(item / K);
+        const int tb = g * G + w;
+        if (tb < a.n_tblocks)
+            pair_item<R, VARD, MIXED>(a, recs[g], recs[G > 1 ? n_groups + tb : g], G > 1, S, sphere,
+                                      part, tb, (int)(item % K));
+    }
 }
 
 // Per target: the K way partials in way order.  A block of 4 waves serves 64 targets; wave w
@@ -320,40 +356,53 @@ __global__ __launch_bounds__(256) void k_fill_zero(double *__restrict__ ux, doub
     if (i < n) { ux[i] = 0.0; uy[i] = 0.0; uz[i] = 0.0; }
 }
 
-// Resident wavefronts per CU of a kernel (queried once per kernel instance).
+// Resident workgroups per CU of a kernel (queried once per kernel instance).
 template <typename Kern>
-int resident_waves(Kern kernel)
+int resident_blocks(Kern kernel, int threads)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)kernel, kWave, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)kernel, threads, 0) != hipSuccess ||
         nb < 1)
-        nb = 4;
+        nb = 1;
     return nb;
 }
 
 template <typename Kern>
-unsigned work_grid(Kern kernel, int &cache, int n_cu, int64_t n_items)
+unsigned work_grid(Kern kernel, int threads, int &cache, int n_cu, int64_t n_items)
 {
-    if (cache == 0) cache = resident_waves(kernel);
+    if (cache == 0) cache = resident_blocks(kernel, threads);
     const int64_t g = (int64_t)n_cu * cache;
     return (unsigned)(g < n_items ? g : n_items);
 }
+
+// Workgroup size (target blocks sharing one cluster stream): the mixed path gains from the
+// shared scalar-cache lines; the FP64 path, whose loop is longer per source, runs one wave per
+// workgroup.
+template <bool MIXED>
+constexpr int group_size() { return MIXED ? 4 : 1; }
 
 template <int R>
 hipError_t launch_r(const PairArgs &a, const PairPlan &p, bool mixed, bool vard, hipStream_t st,
                     const PairTiming *tm)
 {
     static int occ[4] = {0, 0, 0, 0};
+    const int G = mixed ? group_size<true>() : group_size<false>();
+    const int n_groups = (p.n_tblocks + G - 1) / G;
     TBlockRec *rec = reinterpret_cast<TBlockRec *>(a.tblock_scratch);
     uint32_t *ctr = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(a.tblock_scratch) +
                                                  tblock_scratch_bytes(p.n_tblocks) - 256);
     const SrcView &s = a.s;
-    hipLaunchKernelGGL((k_tblock<R>), dim3(p.n_tblocks), dim3(kWave), 0, st, a, rec, (int)mixed, ctr);
+    if (mixed)
+        hipLaunchKernelGGL((k_tblock<R, group_size<true>()>), dim3(n_groups), dim3(kWave), 0, st, a, rec, 1, ctr);
+    else
+        hipLaunchKernelGGL((k_tblock<R, group_size<false>()>), dim3(n_groups), dim3(kWave), 0, st, a, rec, 0, ctr);
     if (tm && tm->e0) (void)hipEventRecord(tm->e0, st);
-    const int64_t n_items = (int64_t)p.n_tblocks * p.n_ways;
+    const int64_t n_items = (int64_t)n_groups * p.n_ways;
 #define SL_PAIR_LAUNCH(V, M, SLOT)                                                                  \
-    hipLaunchKernelGGL((k_pair<R, V, M>), dim3(work_grid(k_pair<R, V, M>, occ[SLOT], p.n_cu, n_items)), \
-                       dim3(kWave), 0, st, a, rec, s.d, s.f32, s.sphere, a.part, ctr)
+    hipLaunchKernelGGL((k_pair<R, V, M, group_size<M>()>),                                           \
+                       dim3(work_grid(k_pair<R, V, M, group_size<M>()>, group_size<M>() * kWave, occ[SLOT], \
+                                      p.n_cu, n_items)),                                             \
+                       dim3(group_size<M>() * kWave), 0, st, a, rec, s.d, s.f32, s.sphere, a.part, ctr)
     if (vard) {
         if (mixed) SL_PAIR_LAUNCH(true, true, 3); else SL_PAIR_LAUNCH(true, false, 1);
     } else {
@@ -366,8 +415,9 @@ hipError_t launch_r(const PairArgs &a, const PairPlan &p, bool mixed, bool vard,
 
 }  // namespace
 
-// Target-block records followed by 256 bytes holding the work counter.
-size_t tblock_scratch_bytes(int n_tblocks) { return (size_t)n_tblocks * sizeof(TBlockRec) + 256; }
+// Target-group and target-block records (at most 2 n_tblocks) followed by 256 bytes holding the
+// work counter.
+size_t tblock_scratch_bytes(int n_tblocks) { return (size_t)2 * n_tblocks * sizeof(TBlockRec) + 256; }
 
 PairPlan plan_pairs(int64_t np_src, int64_t np_tgt, int R, int waves_wanted)
 {

@@ -259,3 +259,27 @@ def test_rho64_parameter(ctx, c2_ref):
         ctx.set_rho64(1.0)
     assert all(e < TOL["mixed"] for e in errs.values()), errs
     assert errs[12.0] < errs[1.0]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_launch_shapes(precision):
+    """Every targets-per-lane and work granularity gives the same sums to the tolerance.  N =
+    6 * 21^2 = 2646 pads to 2816 = 11 blocks of 256: with 4 targets per lane the last workgroup
+    of four blocks is short, and distinct targets (1000 points) pad to a different count."""
+    import oracle
+    import paper_2310_13908_amd as P
+    s = make_surface(RBC, 21)
+    f = sh_force(s.x0, 77)
+    d = 2 * math.pi / 22
+    T = s.X[::3] * 1.01
+    ref = oracle.single_layer(s.X, s.w, f, d)
+    ref_t = oracle.single_layer(s.X, s.w, f, d, targets=T)
+    with P.Context(0) as c:
+        for R in (1, 2, 4):
+            for wps in (1, 3, 16, 32):
+                P.check(P.sl_set_param(c.ptr, P.SL_PARAM_TARGETS_PER_LANE, float(R)))
+                P.check(P.sl_set_param(c.ptr, P.SL_PARAM_WAVES_PER_SIMD, float(wps)))
+                u = gpu_eval(c, s.X, s.w, f, d, precision=precision)
+                assert eps(u, ref) < TOL[precision], (R, wps)
+                u = gpu_eval(c, s.X, s.w, f, d, targets=T, precision=precision)
+                assert eps(u, ref_t) < TOL[precision], (R, wps)

@@ -32,35 +32,6 @@ namespace {
 
 constexpr int kMaxWays = 64;
 
-// Bounding sphere (centre of the box, farthest member, relative margin 2^-40) of the sorted
-// targets [t0, t1), computed by one wave.
-__device__ __forceinline__ void target_sphere(const PairArgs &a, int64_t t0, int64_t t1, double &cx,
-                                              double &cy, double &cz, double &rad, double &dmax)
-{
-    const int lane = threadIdx.x % kWave;
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    dmax = a.delta;
-    bool first = true;
-    for (int64_t i = t0 + lane; i < t1; i += kWave) {
-        const double x = a.t.x[i], y = a.t.y[i], z = a.t.z[i];
-        if (a.t.delta) dmax = first ? a.t.delta[i] : fmax(dmax, a.t.delta[i]);
-        first = false;
-        lo[0] = fmin(lo[0], x); hi[0] = fmax(hi[0], x);
-        lo[1] = fmin(lo[1], y); hi[1] = fmax(hi[1], y);
-        lo[2] = fmin(lo[2], z); hi[2] = fmax(hi[2], z);
-    }
-    cx = 0.5 * (wave_min(lo[0]) + wave_max(hi[0]));
-    cy = 0.5 * (wave_min(lo[1]) + wave_max(hi[1]));
-    cz = 0.5 * (wave_min(lo[2]) + wave_max(hi[2]));
-    double rr = 0.0;
-    for (int64_t i = t0 + lane; i < t1; i += kWave) {
-        const double dx = a.t.x[i] - cx, dy = a.t.y[i] - cy, dz = a.t.z[i] - cz;
-        rr = fmax(rr, fma(dx, dx, fma(dy, dy, __dmul_rn(dz, dz))));
-    }
-    rad = sqrt(wave_max(rr)) * (1.0 + 0x1p-40);
-    dmax = wave_max(dmax);
-}
-
 __device__ __forceinline__ TBlockRec make_rec(const PairArgs &a, int mixed, double cx, double cy,
                                               double cz, double rad, double dmax)
 {
@@ -78,30 +49,70 @@ __device__ __forceinline__ TBlockRec make_rec(const PairArgs &a, int mixed, doub
     return rec;
 }
 
-// Sphere and far threshold of each group of G target blocks (G * 64 R consecutive sorted
-// targets; the last group may be short) and of each of its blocks.  Records: [n_groups] group
-// records, then [n_tblocks] block records.
+// Sphere (centre of the box, farthest member, relative margin 2^-40) and far threshold of each
+// group of G target blocks (G * 64 R consecutive sorted targets; the last group may be short)
+// and, when G > 1, of each of its blocks.  One workgroup per group, wave w on block G g + w.
+// Records: [n_groups] group records, then [n_tblocks] block records.
 template <int R, int G>
-__global__ __launch_bounds__(kWave) void k_tblock(PairArgs a, TBlockRec *__restrict__ out,
-                                                  int mixed, uint32_t *__restrict__ ctr)
+__global__ __launch_bounds__(G * kWave) void k_tblock(PairArgs a, TBlockRec *__restrict__ out,
+                                                      int mixed, uint32_t *__restrict__ ctr)
 {
+    __shared__ double sh[G][8];
     const int g = blockIdx.x;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int n_groups = (a.n_tblocks + G - 1) / G;
+    const int b = g * G + w;
     const int64_t blk = (int64_t)kWave * R;
-    const int64_t np_t = a.t.np;
-    const int64_t t0 = (int64_t)g * G * blk;
-    const int64_t t1 = t0 + G * blk < np_t ? t0 + G * blk : np_t;
-    double cx, cy, cz, rad, dmax;
-    target_sphere(a, t0, t1, cx, cy, cz, rad, dmax);
+    const int64_t t0 = b < a.n_tblocks ? (int64_t)b * blk : 0;
+    const int64_t t1 = b < a.n_tblocks ? t0 + blk : 0;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double dmax = a.t.delta ? 0.0 : a.delta;
+    for (int64_t i = t0 + lane; i < t1; i += kWave) {
+        const double x = a.t.x[i], y = a.t.y[i], z = a.t.z[i];
+        if (a.t.delta) dmax = fmax(dmax, a.t.delta[i]);
+        lo[0] = fmin(lo[0], x); hi[0] = fmax(hi[0], x);
+        lo[1] = fmin(lo[1], y); hi[1] = fmax(hi[1], y);
+        lo[2] = fmin(lo[2], z); hi[2] = fmax(hi[2], z);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { lo[k] = wave_min(lo[k]); hi[k] = wave_max(hi[k]); }
+    dmax = wave_max(dmax);
+    if (lane == 0) {
+        for (int k = 0; k < 3; ++k) { sh[w][k] = lo[k]; sh[w][3 + k] = hi[k]; }
+        sh[w][6] = dmax;
+    }
+    __syncthreads();
+    double glo[3] = {INFINITY, INFINITY, INFINITY}, ghi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double gdmax = 0.0;
+    for (int v = 0; v < G; ++v)
+        if (g * G + v < a.n_tblocks) {
+            for (int k = 0; k < 3; ++k) { glo[k] = fmin(glo[k], sh[v][k]); ghi[k] = fmax(ghi[k], sh[v][3 + k]); }
+            gdmax = fmax(gdmax, sh[v][6]);
+        }
+    const double gx = 0.5 * (glo[0] + ghi[0]), gy = 0.5 * (glo[1] + ghi[1]), gz = 0.5 * (glo[2] + ghi[2]);
+    const double cx = 0.5 * (lo[0] + hi[0]), cy = 0.5 * (lo[1] + hi[1]), cz = 0.5 * (lo[2] + hi[2]);
+    double rr = 0.0, grr = 0.0;
+    for (int64_t i = t0 + lane; i < t1; i += kWave) {
+        const double x = a.t.x[i], y = a.t.y[i], z = a.t.z[i];
+        const double dx = x - cx, dy = y - cy, dz = z - cz;
+        rr = fmax(rr, fma(dx, dx, fma(dy, dy, __dmul_rn(dz, dz))));
+        const double ex = x - gx, ey = y - gy, ez = z - gz;
+        grr = fmax(grr, fma(ex, ex, fma(ey, ey, __dmul_rn(ez, ez))));
+    }
+    rr = wave_max(rr);
+    grr = wave_max(grr);
+    __syncthreads();                 // everyone has read sh[][0..6]
+    if (lane == 0) sh[w][7] = grr;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        out[g] = make_rec(a, mixed, cx, cy, cz, rad, dmax);
+        double gr = 0.0;
+        for (int v = 0; v < G; ++v)
+            if (g * G + v < a.n_tblocks) gr = fmax(gr, sh[v][7]);
+        out[g] = make_rec(a, mixed, gx, gy, gz, sqrt(gr) * (1.0 + 0x1p-40), gdmax);
         if (g == 0) ctr[0] = 0u;   // work counter of k_pair, which runs after this kernel
     }
-    if (G == 1) return;
-    for (int b = 0; b < G && t0 + b * blk < np_t; ++b) {
-        target_sphere(a, t0 + b * blk, t0 + (b + 1) * blk, cx, cy, cz, rad, dmax);
-        if (threadIdx.x == 0) out[n_groups + g * G + b] = make_rec(a, mixed, cx, cy, cz, rad, dmax);
-    }
+    if (G > 1 && lane == 0 && b < a.n_tblocks)
+        out[n_groups + b] = make_rec(a, mixed, cx, cy, cz, sqrt(rr) * (1.0 + 0x1p-40), dmax);
 }
 
 // Source records of the pair kernel ([np][8]: x, y, z, gx, gy, gz, 0, 0).  They arrive as
@@ -393,9 +404,11 @@ hipError_t launch_r(const PairArgs &a, const PairPlan &p, bool mixed, bool vard,
                                                  tblock_scratch_bytes(p.n_tblocks) - 256);
     const SrcView &s = a.s;
     if (mixed)
-        hipLaunchKernelGGL((k_tblock<R, group_size<true>()>), dim3(n_groups), dim3(kWave), 0, st, a, rec, 1, ctr);
+        hipLaunchKernelGGL((k_tblock<R, group_size<true>()>), dim3(n_groups), dim3(group_size<true>() * kWave),
+                           0, st, a, rec, 1, ctr);
     else
-        hipLaunchKernelGGL((k_tblock<R, group_size<false>()>), dim3(n_groups), dim3(kWave), 0, st, a, rec, 0, ctr);
+        hipLaunchKernelGGL((k_tblock<R, group_size<false>()>), dim3(n_groups), dim3(group_size<false>() * kWave),
+                           0, st, a, rec, 0, ctr);
     if (tm && tm->e0) (void)hipEventRecord(tm->e0, st);
     const int64_t n_items = (int64_t)n_groups * p.n_ways;
 #define SL_PAIR_LAUNCH(V, M, SLOT)                                                                  \

@@ -299,7 +299,7 @@ def memory_leg(P, dev, log, n_large=2, n_small=62, passes=2):
                 t0 = time.perf_counter()
                 for k in range(passes):
                     for i, p in enumerate(probs):
-                        np_i = -(-p.N // 256) * 256
+                        np_i = -(-p.N // 256) * 256   # padded nodes: 49 B each resident
                         if i in resident:
                             resident.move_to_end(i)
                         else:
@@ -316,7 +316,7 @@ def memory_leg(P, dev, log, n_large=2, n_small=62, passes=2):
                                     if e.status != P.SL_EBUSY or not (resident or inflight):
                                         raise
                                     make_room(budget, None)   # everything idle goes
-                        make_room((36 if prec == "mixed" else 24) * np_i, i)
+                        make_room(ctx.request_bytes(resident[i], prec), i)
                         f = torch.as_tensor(np.ascontiguousarray(dens[i][k].T), device=dev)
                         u = torch.empty_like(f)
                         cur.synchronize()

@@ -148,6 +148,10 @@ sl_status sl_submit(sl_ctx *ctx, uint64_t handle, sl_precision prec,
                     const double *fx, const double *fy, const double *fz, double mu,
                     double *ux, double *uy, double *uz, uint64_t *request);
 sl_status sl_poll(sl_ctx *ctx, uint64_t request, int *done);
+/* Device memory a request on surface `handle` holds from admission to completion (its staging),
+ * so that a client managing its own budget can make room before submitting.  SL_ENOTFOUND for an
+ * unknown or released handle. */
+sl_status sl_request_bytes(sl_ctx *ctx, uint64_t handle, sl_precision prec, uint64_t *bytes);
 sl_status sl_wait(sl_ctx *ctx, uint64_t request, double timeout_s);
 
 /* Statistics since sl_create (for reporting): serving requests completed, work items

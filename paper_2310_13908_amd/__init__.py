@@ -12,7 +12,8 @@ from ._binding import (EXPORTED, SL_EBUSY, SL_EHIP, SL_EINVAL, SL_ENOMEM, SL_ENO
                        SL_FP64, SL_MIXED, SL_OK, SL_PARAM_KERNEL_TIMING, SL_PARAM_RHO64,
                        SL_PARAM_TARGETS_PER_LANE, SL_PARAM_WAVES_PER_SIMD, SlError, check, load, sl_create,
                        sl_destroy, sl_eval, sl_get_param, sl_get_stats, sl_last_error, sl_poll,
-                       sl_set_param, sl_submit, sl_surface_register, sl_surface_release, sl_wait)
+                       sl_request_bytes, sl_set_param, sl_submit, sl_surface_register,
+                       sl_surface_release, sl_wait)
 
 PRECISIONS = {"fp64": SL_FP64, "mixed": SL_MIXED}
 
@@ -96,6 +97,12 @@ class Context:
 
     def release_surface(self, handle: int):
         check(sl_surface_release(self.ptr, handle), "sl_surface_release")
+
+    def request_bytes(self, handle: int, precision="mixed") -> int:
+        """Device memory a request on this surface holds while admitted (its staging)."""
+        st, b = sl_request_bytes(self.ptr, handle, PRECISIONS[precision])
+        check(st, "sl_request_bytes")
+        return b
 
     def submit(self, handle: int, f, mu=1.0, precision="mixed", out=None):
         """Queue u = S[f] on a resident surface; returns (request id, (3, N) output tensor).

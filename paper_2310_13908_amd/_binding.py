@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "SL_OK", -1: "SL_EINVAL", -2: "SL_ENOMEM", -3: "SL_EBUSY", -4
 # Every symbol include/stokeslet.h declares.
 EXPORTED = ["sl_create", "sl_destroy", "sl_last_error", "sl_set_param", "sl_get_param", "sl_eval",
             "sl_surface_register", "sl_surface_release", "sl_submit", "sl_poll", "sl_wait",
-            "sl_get_stats"]
+            "sl_request_bytes", "sl_get_stats"]
 
 
 class SlError(RuntimeError):
@@ -68,6 +68,7 @@ def load():
         "sl_submit": ([P, u64, i32, V, V, V, d, V, V, V, ctypes.POINTER(u64)], i32),
         "sl_poll": ([P, u64, ctypes.POINTER(i32)], i32),
         "sl_wait": ([P, u64, d], i32),
+        "sl_request_bytes": ([P, u64, i32, ctypes.POINTER(u64)], i32),
         "sl_get_stats": ([P, ctypes.POINTER(sl_stats)], i32),
     }
     for name, (args, res) in sig.items():
@@ -142,6 +143,12 @@ def sl_poll(ctx, request):
 
 def sl_wait(ctx, request, timeout_s: float) -> int:
     return load().sl_wait(ctx, request, timeout_s)
+
+
+def sl_request_bytes(ctx, handle, prec):
+    b = ctypes.c_uint64()
+    st = load().sl_request_bytes(ctx, handle, prec, ctypes.byref(b))
+    return st, b.value
 
 
 def sl_get_stats(ctx) -> sl_stats:

@@ -11,7 +11,8 @@
 //    kind PAIR sums every source of the surface for target block a (128 targets) and writes
 //    u = S[f] for those targets.  A request is published as its gather items followed by its
 //    pair items; pair items wait for the request's gathers (which were claimed earlier, so the
-//    wait is bounded).
+//    wait is bounded).  The request's first gather item copies its descriptor from host memory
+//    into device memory, where the pair items read it (one PCIe read per item instead of ~30).
 //  * One persistent kernel serves all requests: each wavefront claims the next item with a CAS
 //    on a device counter, runs it and counts it done; the wave finishing a request's last item
 //    publishes the request's sequence number to host memory with a system-scope release.
@@ -93,6 +94,8 @@ struct ServeArgs {
     ServeCtl *ctl;
     const WorkItem *ring;
     const ReqDesc *desc;
+    ReqDesc *ddesc;                       // device copies of the descriptors (written by the
+                                          // request's first gather item)
     uint64_t *done_seq;                   // host-pinned, per slot
     DevCounters *dc;
     uint64_t idle_ticks;                  // exit after this long without a claim
@@ -113,6 +116,17 @@ __device__ __forceinline__ uint64_t uni64(uint64_t v)
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
     return ((uint64_t)hi << 32) | lo;
+}
+// A field of a descriptor's device copy, read with a vector load (never through the scalar
+// cache: descriptor slots are reused while the kernel runs) and made wave-uniform.
+template <typename T>
+__device__ __forceinline__ T dfield(const T *p)
+{
+    static_assert(sizeof(T) == 8, "64-bit fields only");
+    const uint64_t v = uni64(__hip_atomic_load((uint64_t *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    T out;
+    memcpy(&out, &v, 8);
+    return out;
 }
 // A descriptor field, read by every lane from host memory and made wave-uniform.
 template <typename T>
@@ -149,6 +163,12 @@ __device__ void run_gather(const ServeArgs &a, const WorkItem &it)
     double *gx = field(&d->gx), *gy = field(&d->gy), *gz = field(&d->gz);
     float *gx32 = field(&d->gx32), *gy32 = field(&d->gy32), *gz32 = field(&d->gz32);
     const int64_t mixed = field(&d->mixed);
+    if (it.a == 0) {   // the request's descriptor, copied once into device memory for its pair items
+        static_assert(sizeof(ReqDesc) % 8 == 0, "descriptor copied in 8-byte words");
+        const uint64_t *src = reinterpret_cast<const uint64_t *>(d);
+        uint64_t *dst = reinterpret_cast<uint64_t *>(a.ddesc + it.slot);
+        for (int k = threadIdx.x; k < (int)(sizeof(ReqDesc) / 8); k += kWave) dst[k] = ld_sys(src + k);
+    }
     for (int64_t p = (int64_t)it.a + threadIdx.x; p < (int64_t)it.b; p += kWave) {
         const int32_t idx = perm[p];
         double vx = 0.0, vy = 0.0, vz = 0.0;
@@ -202,23 +222,24 @@ __device__ void run_pair(const ServeArgs &a, const WorkItem &it)
         return;
     }
 
-    const double *sx = field(&d->x), *sy = field(&d->y), *sz = field(&d->z);
-    const double *gx = field(&d->gx), *gy = field(&d->gy), *gz = field(&d->gz);
-    const float *sx32 = field(&d->x32), *sy32 = field(&d->y32), *sz32 = field(&d->z32);
-    const float *gx32 = field(&d->gx32), *gy32 = field(&d->gy32), *gz32 = field(&d->gz32);
-    const int32_t *perm = field(&d->perm);
-    const double4 *sphere = field(&d->sphere);
-    const TBlockRec *tbr = field(&d->tbr);
-    double *ux = field(&d->ux), *uy = field(&d->uy), *uz = field(&d->uz);
-    const int64_t np = field(&d->np);
-    const double delta = field(&d->delta), scale = field(&d->scale);
-    const int64_t mixed = field(&d->mixed);
+    const ReqDesc *dd = a.ddesc + it.slot;   // written before the gathers finished
+    const double *sx = dfield(&dd->x), *sy = dfield(&dd->y), *sz = dfield(&dd->z);
+    const double *gx = dfield(&dd->gx), *gy = dfield(&dd->gy), *gz = dfield(&dd->gz);
+    const float *sx32 = dfield(&dd->x32), *sy32 = dfield(&dd->y32), *sz32 = dfield(&dd->z32);
+    const float *gx32 = dfield(&dd->gx32), *gy32 = dfield(&dd->gy32), *gz32 = dfield(&dd->gz32);
+    const int32_t *perm = dfield(&dd->perm);
+    const double4 *sphere = dfield(&dd->sphere);
+    const TBlockRec *tbr = dfield(&dd->tbr);
+    double *ux = dfield(&dd->ux), *uy = dfield(&dd->uy), *uz = dfield(&dd->uz);
+    const int64_t np = dfield(&dd->np);
+    const double delta = dfield(&dd->delta), scale = dfield(&dd->scale);
+    const int64_t mixed = dfield(&dd->mixed);
 
     const int64_t t0 = (int64_t)it.a * kServeBlock;
     const TBlockRec rec = tbr[it.a];
     const double gap_far = mixed ? rec.gap_far_mixed : rec.gap_far;
     const DeltaC dc = make_delta(delta);
-    const DeltaC32 dc32 = make_delta32(delta, field(&d->rho64));
+    const DeltaC32 dc32 = make_delta32(delta, dfield(&dd->rho64));
     double tx[R], ty[R], tz[R], ax[R], ay[R], az[R];
     float tx32[R], ty32[R], tz32[R], hx[R], hy[R], hz[R], lx[R], ly[R], lz[R];
 #pragma unroll
@@ -317,12 +338,12 @@ __device__ void run_pair(const ServeArgs &a, const WorkItem &it)
     }
     __threadfence();
     if (lane == 0) {
-        const uint64_t items_target = ld_sys(&d->items_target);
+        const uint64_t items_target = dfield(&dd->items_target);
         const uint64_t old = __hip_atomic_fetch_add(&a.dc->items_done[it.slot], 1ull,
                                                     __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (old + 1 == items_target) {
             __threadfence_system();
-            __hip_atomic_store(&a.done_seq[it.slot], ld_sys(&d->seq), __ATOMIC_RELEASE,
+            __hip_atomic_store(&a.done_seq[it.slot], dfield(&dd->seq), __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
@@ -596,6 +617,7 @@ struct Server {
     ReqDesc *desc = nullptr;
     uint64_t *done_seq = nullptr;
     DevCounters *dc = nullptr;
+    ReqDesc *ddesc = nullptr;             // device copies of the descriptors
     uint64_t gathers_cum[kMaxSlots] = {};
     uint64_t items_cum[kMaxSlots] = {};
     std::vector<int> free_slots;
@@ -651,6 +673,7 @@ sl_status Server::init(sl_ctx *c)
     memset((void *)desc, 0, sizeof(ReqDesc) * kMaxSlots);
     memset((void *)done_seq, 0, sizeof(uint64_t) * kMaxSlots);
     SL_HIP(hipMalloc((void **)&dc, sizeof(DevCounters)));
+    SL_HIP(hipMalloc((void **)&ddesc, sizeof(ReqDesc) * kMaxSlots));
     SL_HIP(hipMemsetAsync(dc, 0, sizeof(DevCounters), aux));
     size_t bytes = ctx->budget;
     SL_HIP(hipMalloc((void **)&arena_mem, bytes));
@@ -675,6 +698,7 @@ void Server::shutdown()
     if (aux) (void)hipStreamSynchronize(aux);
     if (arena_mem) (void)hipFree(arena_mem);
     if (dc) (void)hipFree(dc);
+    if (ddesc) (void)hipFree(ddesc);
     if (ctl) (void)hipHostFree(ctl);
     if (ring) (void)hipHostFree(ring);
     if (desc) (void)hipHostFree(desc);
@@ -789,7 +813,7 @@ sl_status Server::ensure_kernel_locked()
         if (q == hipErrorNotReady) return SL_OK;          // still running
         if (q != hipSuccess) return hip_fail(q, "serving kernel");
     }
-    ServeArgs a{ctl, ring, desc, done_seq, dc,
+    ServeArgs a{ctl, ring, desc, ddesc, done_seq, dc,
                 (uint64_t)(kIdleSeconds * clock_hz), (uint64_t)(kGatherWaitSeconds * clock_hz),
                 (uint64_t)(kPollSeconds * clock_hz) + 1, stats.kernel_launches + 1};
     // All waves resident at once (so that they share one idle clock), at most kServeWavesPerSimd
@@ -998,6 +1022,20 @@ sl_status sl_surface_release(sl_ctx *ctx, uint64_t handle)
         return fail(SL_ENOTFOUND, "sl_surface_release: unknown handle");
     it->second.released = true;
     if (it->second.refs == 0) s->free_surface_locked(handle);
+    return SL_OK;
+}
+
+sl_status sl_request_bytes(sl_ctx *ctx, uint64_t handle, sl_precision prec, uint64_t *bytes)
+{
+    if (!ctx || !bytes) return fail(SL_EINVAL, "sl_request_bytes: NULL argument");
+    if (prec != SL_FP64 && prec != SL_MIXED) return fail(SL_EINVAL, "sl_request_bytes: unknown precision");
+    Server *s = ctx->server;
+    if (!s) return fail(SL_ENOTFOUND, "sl_request_bytes: unknown surface");
+    std::lock_guard<std::mutex> l(s->mu);
+    auto it = s->surfaces.find(handle);
+    if (it == s->surfaces.end() || it->second.released)
+        return fail(SL_ENOTFOUND, "sl_request_bytes: unknown surface");
+    *bytes = (uint64_t)staging_bytes(it->second.np, prec == SL_MIXED);
     return SL_OK;
 }
 

@@ -86,13 +86,16 @@ def test_admission_under_small_budget(surfaces, refs):
     s, f, d = surfaces[2]
     np_pad = ((s.N + 255) // 256) * 256
     surf_bytes = np_pad * (4 * 8 + 3 * 4 + 4) + np_pad // 64 * 32 + np_pad // 128 * 64 + 8 * 256
-    stage = np_pad * (3 * 8 + 3 * 4) + 6 * 256
-    budget = surf_bytes + stage + stage // 5          # one request's staging at a time
-    with P.Context(0, hbm_budget_bytes=budget) as c:
-        h = c.register_surface(dev_t(s.X), dev_t(s.w), d)
+    with P.Context(0) as c0:                          # one request's staging, as the library sizes it
+        stage = c0.request_bytes(c0.register_surface(dev_t(s.X), dev_t(s.w), d), "mixed")
+    with P.Context(0, hbm_budget_bytes=surf_bytes + surf_bytes // 2) as c:
+        c.register_surface(dev_t(s.X), dev_t(s.w), d)
         with pytest.raises(P.SlError) as ei:           # a second copy does not fit
             c.register_surface(dev_t(s.X), dev_t(s.w), d)
         assert ei.value.status == P.SL_EBUSY
+    budget = surf_bytes + stage + stage // 5          # one request's staging at a time
+    with P.Context(0, hbm_budget_bytes=budget) as c:
+        h = c.register_surface(dev_t(s.X), dev_t(s.w), d)
         rids = [c.submit(h, dev_t(f * (k + 1)), mu=0.8, precision="mixed")[0] for k in range(8)]
         for k, rid in enumerate(rids):
             u = c.wait(rid, 120.0).cpu().numpy()
@@ -165,3 +168,19 @@ def test_register_while_kernel_busy(ctx, surfaces, refs):
         assert eps(ctx.wait(rid, 60.0).cpu().numpy(), refs[2]) < TOL["fp64"]
     assert eps(ctx.wait(rid2, 60.0).cpu().numpy(), refs[1]) < TOL["fp64"]
     assert ctx.stats().kernel_launches >= n0
+
+
+def test_request_bytes(ctx, surfaces):
+    """The staging a request holds: positive, larger in mixed (single-precision copies too), and
+    refused for an unknown handle."""
+    import paper_2310_13908_amd as P
+    s, f, d = surfaces[1]
+    h = ctx.register_surface(dev_t(s.X), dev_t(s.w), d)
+    b64 = ctx.request_bytes(h, "fp64")
+    b32 = ctx.request_bytes(h, "mixed")
+    assert 24 * s.N <= b64 < b32
+    st, _ = P.sl_request_bytes(ctx.ptr, h + 1000, P.SL_FP64)
+    assert st == P.SL_ENOTFOUND
+    ctx.release_surface(h)
+    st, _ = P.sl_request_bytes(ctx.ptr, h, P.SL_FP64)
+    assert st == P.SL_ENOTFOUND

@@ -66,15 +66,18 @@ def time_steps(fn, steps, warmup):
 
 
 def measure_precision(ctx, P, prob, tens, precision, steps, warmup):
-    """ms per full evaluation, and the average pair-kernel duration from the library's events."""
+    """ms per full evaluation (steps timed back to back), and the average pair-kernel duration
+    from the events the library records around its launch (a second pass: the events themselves
+    add a few microseconds per evaluation, so they stay out of the timed steps)."""
+    import torch
     X, w, F = tens
-    out = __import__("torch").empty((3, prob.N), dtype=__import__("torch").float64, device=X.device)
+    out = torch.empty((3, prob.N), dtype=torch.float64, device=X.device)
     fn = lambda: ctx.single_layer(X, w, F, prob.delta, precision=precision, out=out)
-    for _ in range(warmup):
-        fn()
+    t = time_steps(fn, steps, warmup)
     s0 = P.sl_get_stats(ctx.ptr)
     P.check(P.sl_set_param(ctx.ptr, P.SL_PARAM_KERNEL_TIMING, 1.0))
-    t = time_steps(fn, steps, 0)
+    n_timed = max(3, min(steps, 20))
+    time_steps(fn, n_timed, 0)
     P.check(P.sl_set_param(ctx.ptr, P.SL_PARAM_KERNEL_TIMING, 0.0))
     s1 = P.sl_get_stats(ctx.ptr)
     launches = max(1, s1.pair_launches - s0.pair_launches)

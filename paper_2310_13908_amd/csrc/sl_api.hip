@@ -274,11 +274,32 @@ sl_status sl_eval(sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *s
     SL_HIP(hipMallocAsync((void **)&base, bytes, st));
     carve(base, ws, n_sort, np_s, np_t, !same, mixed, vard, plan.n_ways);
 
+    double rho64;
+    {
+        std::lock_guard<std::mutex> l(ctx->mu);
+        rho64 = ctx->rho64;
+    }
+    // far clusters: s = 1 to the working precision, and (mixed) outside the FP64 zone
+    const double far_cut = mixed ? std::max(kRhoExact32, rho64) : kRhoExact64;
+    // targets = sources with one delta: the source gather also writes the target records
+    TRecOut trec = {};
+    const int G = pair_group_size(mixed);
+    if (same && !vard && plan.R * G <= 4) {
+        trec.rec = reinterpret_cast<TBlockRec *>(ws.tblock);
+        trec.ctr = pair_counter(ws.tblock, plan.n_tblocks);
+        trec.bbox = ws.ps.bbox;
+        trec.gap_far = far_cut * delta;
+        trec.R = plan.R;
+        trec.G = G;
+        trec.n_tblocks = plan.n_tblocks;
+        trec.mixed = mixed ? 1 : 0;
+    }
+
     hipError_t e = launch_bbox(sx, sy, sz, n_src, tx, ty, tz, same ? 0 : n_tgt, ws.ps, st);
     const uint32_t *order = nullptr;
     if (e == hipSuccess) e = launch_sort_points(sx, sy, sz, n_src, ws.ps, &order, st);
     if (e == hipSuccess)
-        e = launch_gather_src(order, n_src, np_s, sx, sy, sz, w, fx, fy, fz, ws.ps.centre, ws.so, st);
+        e = launch_gather_src(order, n_src, np_s, sx, sy, sz, w, fx, fy, fz, ws.ps.centre, ws.so, trec, st);
     TgtView tv;
     if (same) {
         tv.x = ws.so.x; tv.y = ws.so.y; tv.z = ws.so.z;
@@ -306,12 +327,9 @@ sl_status sl_eval(sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *s
     pa.s = SrcView{ws.so.d, ws.so.f32, ws.so.sphere, np_s};
     pa.t = tv;
     pa.delta = vard ? 1.0 : delta;
-    {
-        std::lock_guard<std::mutex> l(ctx->mu);
-        pa.rho64 = ctx->rho64;
-    }
-    // far clusters: s = 1 to the working precision, and (mixed) outside the FP64 zone
-    pa.far_cut = mixed ? std::max(kRhoExact32, pa.rho64) : kRhoExact64;
+    pa.rho64 = rho64;
+    pa.far_cut = far_cut;
+    pa.records_ready = trec.rec ? 1 : 0;
     pa.n_tblocks = plan.n_tblocks;
     pa.n_ways = plan.n_ways;
     pa.part = ws.part;

@@ -70,6 +70,8 @@ struct PairArgs {
     const double *bbox;      // [6] box of all points (min xyz, max xyz): bounds the rounding
                              // of the single-precision positions in the mixed path
     void *tblock_scratch;    // tblock_scratch_bytes(n_tblocks): per-target-block spheres
+    int records_ready;       // 1: the source gather already wrote the target records (and
+                             // zeroed the work counter), so launch_pair skips k_tblock
 };
 
 // Optional events recorded around the pair kernel.
@@ -87,6 +89,10 @@ struct PairPlan {
 };
 
 PairPlan plan_pairs(int64_t np_src, int64_t np_tgt, int R, int waves_wanted);
+// Target blocks per workgroup of the pair kernel (they share one cluster stream).
+int pair_group_size(bool mixed);
+// The pair kernel's work counter inside tblock_scratch.
+uint32_t *pair_counter(void *tblock_scratch, int n_tblocks);
 
 hipError_t launch_pair(const PairArgs &a, const PairPlan &p, bool mixed, bool var_delta,
                        hipStream_t st, const PairTiming *tm);
@@ -103,6 +109,7 @@ struct PackScratch {
     uint32_t *counts[3];     // [256 * n_chunks] digit counts of each sort pass
     int64_t n_counts;
     double *bbox_part;       // [kBboxBlocks * 6]
+    int n_bbox_parts;        // partials written by the last launch_bbox
     double *bbox;            // [6]: min x, y, z, max x, y, z
     double *centre;          // [3]: bounding-box centre (origin of the single-precision copies)
 };
@@ -110,10 +117,11 @@ struct PackScratch {
 size_t sort_scratch_bytes(int64_t n);
 void carve_sort_scratch(void *base, int64_t n, PackScratch &ps);
 
-// Bounding box of up to two point sets (b may be empty), written to ps.bbox / ps.centre.
+// Bounding box of up to two point sets (b may be empty): per-block partials, folded into
+// ps.bbox / ps.centre by the first launch_sort_points that follows (before any reader).
 hipError_t launch_bbox(const double *ax, const double *ay, const double *az, int64_t na,
                        const double *bx, const double *by, const double *bz, int64_t nb,
-                       const PackScratch &ps, hipStream_t st);
+                       PackScratch &ps, hipStream_t st);
 // Morton order of n points: on return *order points to n indices (sorted by key, stable).
 hipError_t launch_sort_points(const double *x, const double *y, const double *z, int64_t n,
                               const PackScratch &ps, const uint32_t **order, hipStream_t st);
@@ -126,11 +134,21 @@ struct SrcOut {
     double4 *sphere;
     int32_t *perm;                                  // optional: sorted -> caller index (-1 pad)
 };
+// Target-group and target-block records of the pair kernel, written by the source gather when the
+// targets are the sources (rec == nullptr: not written).  Needs R * G <= 4, so that a workgroup
+// of 256 gathered points holds whole groups.
+struct TRecOut {
+    TBlockRec *rec;          // [n_groups] group records, then [n_tblocks] block records if G > 1
+    uint32_t *ctr;           // the pair kernel's work counter, zeroed here
+    const double *bbox;      // box of all points
+    double gap_far;          // far_cut * delta
+    int R, G, n_tblocks, mixed;
+};
 // g = w * f gathered in `order`; w may be nullptr when `wf_premul` (f already holds w*f).
 hipError_t launch_gather_src(const uint32_t *order, int64_t n, int64_t np, const double *x,
                              const double *y, const double *z, const double *w, const double *fx,
                              const double *fy, const double *fz, const double *centre,
-                             const SrcOut &o, hipStream_t st);
+                             const SrcOut &o, const TRecOut &t, hipStream_t st);
 
 struct TgtOut {
     double *x, *y, *z;

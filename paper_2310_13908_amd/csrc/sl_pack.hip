@@ -3,7 +3,8 @@
 // The pair kernels classify whole blocks of targets against clusters of 64 sources as
 // "far" (plain Stokeslet, no erf/exp) or "near" (regularized), which only pays off when
 // consecutive points are close in space.  Packing therefore:
-//   1. takes the bounding box of all points (two-pass, deterministic),
+//   1. takes the bounding box of all points (partials per block, folded in a fixed order by the
+//      Morton-key kernel: deterministic),
 //   2. orders the points along a 24-bit Morton curve (stable LSD radix sort, three passes of
 //      8-bit digits; each pass's digit histogram is counted by the kernel that writes the
 //      pass's input, so a pass is two launches: scan and scatter),
@@ -63,25 +64,6 @@ __global__ __launch_bounds__(kBboxThreads) void k_bbox_partial(
     }
 }
 
-__global__ __launch_bounds__(kWave) void k_bbox_final(const double *__restrict__ part, int nparts,
-                                                      double *__restrict__ bbox,
-                                                      double *__restrict__ centre)
-{
-    const int lane = threadIdx.x;
-    double v[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) v[k] = k < 3 ? INFINITY : -INFINITY;
-    for (int j = lane; j < nparts; j += kWave)
-#pragma unroll
-        for (int k = 0; k < 6; ++k) v[k] = k < 3 ? fmin(v[k], part[j * 6 + k]) : fmax(v[k], part[j * 6 + k]);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) v[k] = k < 3 ? wave_min(v[k]) : wave_max(v[k]);
-    if (lane == 0) {
-        for (int k = 0; k < 6; ++k) bbox[k] = v[k];
-        for (int k = 0; k < 3; ++k) centre[k] = 0.5 * (v[k] + v[k + 3]);
-    }
-}
-
 // ----------------------------------------------------------------------------------------
 // Morton keys
 // ----------------------------------------------------------------------------------------
@@ -108,25 +90,53 @@ __device__ __forceinline__ uint32_t morton3(uint32_t qx, uint32_t qy, uint32_t q
     return k;
 }
 
-// Keys, identity values, and the digit counts of the first sort pass (counts[digit * nblocks +
-// block], block = i / kSortChunk; integer atomics, so the counts do not depend on their order).
+// Every block first folds the bounding-box partials (in the same order, so every block gets the
+// same box; block 0 also stores it with its centre for the later kernels).  Then: keys, identity
+// values, and the digit counts of the first sort pass (counts[digit * nblocks + block], block =
+// i / kSortChunk; integer atomics, so the counts do not depend on their order).
 __global__ __launch_bounds__(256) void k_morton(const double *__restrict__ x,
                                                 const double *__restrict__ y,
                                                 const double *__restrict__ z, int64_t n,
-                                                const double *__restrict__ bbox,
+                                                const double *__restrict__ bbox_part, int nparts,
+                                                double *__restrict__ bbox_out,
+                                                double *__restrict__ centre_out,
                                                 uint32_t *__restrict__ keys,
                                                 uint32_t *__restrict__ vals,
                                                 uint32_t *__restrict__ counts, int nblocks)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t qx = quantize(x[i], bbox[0], bbox[3]);
-    const uint32_t qy = quantize(y[i], bbox[1], bbox[4]);
-    const uint32_t qz = quantize(z[i], bbox[2], bbox[5]);
-    const uint32_t k = morton3(qx, qy, qz);
-    keys[i] = k;
-    vals[i] = (uint32_t)i;
-    atomicAdd(&counts[(int64_t)(k & 255u) * nblocks + i / kSortChunk], 1u);
+    __shared__ double box[6];
+    __shared__ double red[4][6];
+    {   // one partial per thread (nparts <= 256), min / max over the block: order-independent
+        double v[6];
+        for (int k = 0; k < 6; ++k) v[k] = k < 3 ? INFINITY : -INFINITY;
+        if ((int)threadIdx.x < nparts)
+            for (int k = 0; k < 6; ++k) v[k] = bbox_part[threadIdx.x * 6 + k];
+        for (int k = 0; k < 6; ++k) v[k] = k < 3 ? wave_min(v[k]) : wave_max(v[k]);
+        const int wv = threadIdx.x / kWave;
+        if (threadIdx.x % kWave == 0)
+            for (int k = 0; k < 6; ++k) red[wv][k] = v[k];
+        __syncthreads();
+        if (threadIdx.x < 6) {
+            const int k = threadIdx.x;
+            double r = red[0][k];
+            for (int j = 1; j < 4; ++j) r = k < 3 ? fmin(r, red[j][k]) : fmax(r, red[j][k]);
+            box[k] = r;
+        }
+        __syncthreads();
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 6) {
+        bbox_out[threadIdx.x] = box[threadIdx.x];
+        if (threadIdx.x < 3) centre_out[threadIdx.x] = 0.5 * (box[threadIdx.x] + box[threadIdx.x + 3]);
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t qx = quantize(x[i], box[0], box[3]);
+        const uint32_t qy = quantize(y[i], box[1], box[4]);
+        const uint32_t qz = quantize(z[i], box[2], box[5]);
+        const uint32_t k = morton3(qx, qy, qz);
+        keys[i] = k;
+        vals[i] = (uint32_t)i;
+        atomicAdd(&counts[(int64_t)(k & 255u) * nblocks + i / kSortChunk], 1u);
+    }
 }
 
 // ----------------------------------------------------------------------------------------
@@ -223,7 +233,7 @@ __global__ __launch_bounds__(256) void k_gather_src(
     const uint32_t *__restrict__ order, int64_t n, int64_t np, const double *__restrict__ x,
     const double *__restrict__ y, const double *__restrict__ z, const double *__restrict__ w,
     const double *__restrict__ fx, const double *__restrict__ fy, const double *__restrict__ fz,
-    const double *__restrict__ centre, SrcOut o)
+    const double *__restrict__ centre, SrcOut o, TRecOut t)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // np % 256 == 0
     const bool real = p < n;
@@ -245,12 +255,57 @@ __global__ __launch_bounds__(256) void k_gather_src(
     if (o.perm) o.perm[p] = real ? (int32_t)idx : -1;
     // Cluster sphere: centre of the cluster's box, radius = farthest member (+ a relative
     // margin so that rounding never shrinks it).
-    const double cx = 0.5 * (wave_min(px) + wave_max(px));
-    const double cy = 0.5 * (wave_min(py) + wave_max(py));
-    const double cz = 0.5 * (wave_min(pz) + wave_max(pz));
+    const double lo[3] = {wave_min(px), wave_min(py), wave_min(pz)};
+    const double hi[3] = {wave_max(px), wave_max(py), wave_max(pz)};
+    const double cx = 0.5 * (lo[0] + hi[0]), cy = 0.5 * (lo[1] + hi[1]), cz = 0.5 * (lo[2] + hi[2]);
     const double dx = px - cx, dy = py - cy, dz = pz - cz;
     const double rad = sqrt(wave_max(dx * dx + dy * dy + dz * dz)) * (1.0 + 0x1p-40);
-    if ((threadIdx.x % kWave) == 0) o.sphere[p / kCluster] = make_double4(cx, cy, cz, rad);
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    if (lane == 0) o.sphere[p / kCluster] = make_double4(cx, cy, cz, rad);
+    if (!t.rec) return;
+    // Targets = sources: the pair kernel's target-group and target-block spheres from the same
+    // points (box centre, farthest member, margin), as its own record kernel computes them.
+    __shared__ double sh[4][8];
+    if (lane == 0)
+        for (int k = 0; k < 3; ++k) { sh[wv][k] = lo[k]; sh[wv][3 + k] = hi[k]; }
+    __syncthreads();
+    const int R = t.R, RG = t.R * t.G;
+    const int wb = wv / R * R, wg = wv / RG * RG;    // first wave of this block / group
+    double bl[3], bh[3], gl[3], gh[3];
+    for (int k = 0; k < 3; ++k) { bl[k] = gl[k] = INFINITY; bh[k] = gh[k] = -INFINITY; }
+    for (int v = wg; v < wg + RG; ++v)
+        for (int k = 0; k < 3; ++k) {
+            gl[k] = fmin(gl[k], sh[v][k]); gh[k] = fmax(gh[k], sh[v][3 + k]);
+            if (v >= wb && v < wb + R) { bl[k] = fmin(bl[k], sh[v][k]); bh[k] = fmax(bh[k], sh[v][3 + k]); }
+        }
+    const double bx = 0.5 * (bl[0] + bh[0]), by = 0.5 * (bl[1] + bh[1]), bz = 0.5 * (bl[2] + bh[2]);
+    const double gx0 = 0.5 * (gl[0] + gh[0]), gy0 = 0.5 * (gl[1] + gh[1]), gz0 = 0.5 * (gl[2] + gh[2]);
+    const double ex = px - bx, ey = py - by, ez = pz - bz;
+    const double fx0 = px - gx0, fy0 = py - gy0, fz0 = pz - gz0;
+    const double rb = wave_max(fma(ex, ex, fma(ey, ey, __dmul_rn(ez, ez))));
+    const double rg = wave_max(fma(fx0, fx0, fma(fy0, fy0, __dmul_rn(fz0, fz0))));
+    __syncthreads();                 // every wave has read the boxes
+    if (lane == 0) { sh[wv][6] = rb; sh[wv][7] = rg; }
+    __syncthreads();
+    double gap_far = t.gap_far;
+    if (t.mixed) {
+        const double ux = t.bbox[3] - t.bbox[0], uy = t.bbox[4] - t.bbox[1], uz = t.bbox[5] - t.bbox[2];
+        gap_far = fmax(gap_far, 0x1p-10 * sqrt(fma(ux, ux, fma(uy, uy, __dmul_rn(uz, uz)))));
+    }
+    const int n_groups = t.n_tblocks / t.G;
+    if (lane == 0 && wv == wg) {
+        double r2 = 0.0;
+        for (int v = wg; v < wg + RG; ++v) r2 = fmax(r2, sh[v][7]);
+        TBlockRec rec = {gx0, gy0, gz0, sqrt(r2) * (1.0 + 0x1p-40), gap_far, gap_far, 0.0, 0.0};
+        t.rec[blockIdx.x * (4 / RG) + wv / RG] = rec;
+    }
+    if (t.G > 1 && lane == 0 && wv == wb) {
+        double r2 = 0.0;
+        for (int v = wb; v < wb + R; ++v) r2 = fmax(r2, sh[v][6]);
+        TBlockRec rec = {bx, by, bz, sqrt(r2) * (1.0 + 0x1p-40), gap_far, gap_far, 0.0, 0.0};
+        t.rec[n_groups + blockIdx.x * (4 / R) + wv / R] = rec;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *t.ctr = 0u;
 }
 
 __global__ __launch_bounds__(256) void k_gather_tgt(
@@ -325,15 +380,14 @@ void carve_sort_scratch(void *base, int64_t n, PackScratch &ps)
 
 hipError_t launch_bbox(const double *ax, const double *ay, const double *az, int64_t na,
                        const double *bx, const double *by, const double *bz, int64_t nb,
-                       const PackScratch &ps, hipStream_t st)
+                       PackScratch &ps, hipStream_t st)
 {
     const int64_t tot = na + nb;
     int blocks = (int)((tot + kBboxThreads - 1) / kBboxThreads);
     blocks = blocks < 1 ? 1 : (blocks > kBboxBlocks ? kBboxBlocks : blocks);
     hipLaunchKernelGGL(k_bbox_partial, dim3(blocks), dim3(kBboxThreads), 0, st, ax, ay, az, na,
                        bx, by, bz, nb, ps.bbox_part, ps.counts[0], ps.n_counts);
-    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kWave), 0, st, ps.bbox_part, blocks, ps.bbox,
-                       ps.centre);
+    ps.n_bbox_parts = blocks;   // folded by k_morton
     return hipGetLastError();
 }
 
@@ -343,8 +397,10 @@ hipError_t launch_sort_points(const double *x, const double *y, const double *z,
                               const PackScratch &ps, const uint32_t **order, hipStream_t st)
 {
     const int nb = sort_blocks(n);
-    hipLaunchKernelGGL(k_morton, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, y, z, n,
-                       ps.bbox, ps.keys[0], ps.vals[0], ps.counts[0], nb);
+    const int64_t mb = (n + 255) / 256;
+    hipLaunchKernelGGL(k_morton, dim3((unsigned)(mb < 1024 ? mb : 1024)), dim3(256), 0, st, x, y, z, n,
+                       ps.bbox_part, ps.n_bbox_parts, ps.bbox, ps.centre, ps.keys[0], ps.vals[0],
+                       ps.counts[0], nb);
     int cur = 0;
     for (int p = 0; p < kPasses; ++p) {
         hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, ps.counts[p], (int64_t)256 * nb,
@@ -361,10 +417,11 @@ hipError_t launch_sort_points(const double *x, const double *y, const double *z,
 hipError_t launch_gather_src(const uint32_t *order, int64_t n, int64_t np, const double *x,
                              const double *y, const double *z, const double *w, const double *fx,
                              const double *fy, const double *fz, const double *centre,
-                             const SrcOut &o, hipStream_t st)
+                             const SrcOut &o, const TRecOut &t, hipStream_t st)
 {
+    if (t.rec && (t.R * t.G > 4 || 4 % (t.R * t.G) != 0)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_gather_src, dim3((unsigned)(np / 256)), dim3(256), 0, st, order, n, np,
-                       x, y, z, w, fx, fy, fz, centre, o);
+                       x, y, z, w, fx, fy, fz, centre, o, t);
     return hipGetLastError();
 }
 

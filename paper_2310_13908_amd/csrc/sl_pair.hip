@@ -403,12 +403,15 @@ hipError_t launch_r(const PairArgs &a, const PairPlan &p, bool mixed, bool vard,
     uint32_t *ctr = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(a.tblock_scratch) +
                                                  tblock_scratch_bytes(p.n_tblocks) - 256);
     const SrcView &s = a.s;
-    if (mixed)
+    if (a.records_ready) {
+        // written by the source gather
+    } else if (mixed) {
         hipLaunchKernelGGL((k_tblock<R, group_size<true>()>), dim3(n_groups), dim3(group_size<true>() * kWave),
                            0, st, a, rec, 1, ctr);
-    else
+    } else {
         hipLaunchKernelGGL((k_tblock<R, group_size<false>()>), dim3(n_groups), dim3(group_size<false>() * kWave),
                            0, st, a, rec, 0, ctr);
+    }
     if (tm && tm->e0) (void)hipEventRecord(tm->e0, st);
     const int64_t n_items = (int64_t)n_groups * p.n_ways;
 #define SL_PAIR_LAUNCH(V, M, SLOT)                                                                  \
@@ -431,6 +434,14 @@ hipError_t launch_r(const PairArgs &a, const PairPlan &p, bool mixed, bool vard,
 // Target-group and target-block records (at most 2 n_tblocks) followed by 256 bytes holding the
 // work counter.
 size_t tblock_scratch_bytes(int n_tblocks) { return (size_t)2 * n_tblocks * sizeof(TBlockRec) + 256; }
+
+int pair_group_size(bool mixed) { return mixed ? group_size<true>() : group_size<false>(); }
+
+uint32_t *pair_counter(void *tblock_scratch, int n_tblocks)
+{
+    return reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(tblock_scratch) +
+                                        tblock_scratch_bytes(n_tblocks) - 256);
+}
 
 PairPlan plan_pairs(int64_t np_src, int64_t np_tgt, int R, int waves_wanted)
 {

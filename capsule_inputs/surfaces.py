@@ -16,7 +16,7 @@ capsule using regularized Stokes kernels and overset finite differences"):
 * trapezoid-POU rule: weight psi W h^2 ..................... Sec. 3.3, eq. (smoothint)
 * area element W = |x_u x x_v| ............................. Appendix B (differential formulas)
 
-Readings where the paper is silent (listed in the design doc as well):
+Readings where the paper is silent:
 
 * "n x n points per patch" means m = n + 1, h = pi / (n + 1).
 * W is evaluated from the analytic chart derivatives (the paper approximates the

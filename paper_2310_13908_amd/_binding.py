@@ -49,7 +49,7 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it first "
-                          "(python -c 'import __graft_entry__ as g; g.build()')")
+                          "(python -m paper_2310_13908_amd.build)")
     # torch provides the device memory and streams the library works on; load its HIP runtime
     # first so that the library binds to the same runtime instance (one libamdhip64 per process).
     import torch  # noqa: F401

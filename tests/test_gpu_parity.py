@@ -283,3 +283,32 @@ def test_launch_shapes(precision):
                 assert eps(u, ref) < TOL[precision], (R, wps)
                 u = gpu_eval(c, s.X, s.w, f, d, targets=T, precision=precision)
                 assert eps(u, ref_t) < TOL[precision], (R, wps)
+
+
+@pytest.fixture(scope="module")
+def c5_large():
+    """One capsule of the memory-admitted stream at its full size: ellipsoid 1:0.8:0.5,
+    6 x 512 x 512 nodes (N = 1,572,864), SH density, delta = 2h; 64 sampled targets."""
+    import oracle
+    p = W.shape_sh(ELLIPSOID_SERVING, 512, W.SEED_C5)
+    idx = np.sort(np.random.default_rng(W.SEED_C5).choice(p.N, size=64, replace=False))
+    ref = oracle.single_layer(p.surface.X, p.surface.w, p.f, p.delta, targets=p.surface.X[idx])
+    return p, idx, ref
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_largest_capsule_one_shot_and_served(ctx, c5_large, precision):
+    """The largest surface of the workloads through sl_eval and through the serving path, on
+    sampled targets recomputed by the oracle over all 1.57 M sources."""
+    import torch
+    p, idx, ref = c5_large
+    u = gpu_eval(ctx, p.surface.X, p.surface.w, p.f, p.delta, precision=precision)
+    assert eps(u[idx], ref) < TOL[precision]
+    assert np.all(np.isfinite(u))
+    dev = torch.device("cuda", 0)
+    t = lambda a: torch.as_tensor(np.asarray(a, dtype=np.float64), device=dev)
+    h = ctx.register_surface(t(p.surface.X), t(p.surface.w), p.delta)
+    rid, _ = ctx.submit(h, t(p.f), precision=precision)
+    us = ctx.wait(rid, 120.0).cpu().numpy()
+    ctx.release_surface(h)
+    assert eps(us[idx], ref) < TOL[precision]

@@ -16,8 +16,12 @@ The device code splits the regularized zone p = r/delta < 6.9 in two:
   e^{-q} |g_fit - g| is what perturbs s.  e^{-q} = 2^-n e^{-f}, n = rint(q / ln 2),
   |f| <= ln2/2, with e^x on |x| <= ln2/2 interpolated at Chebyshev nodes.
 
-The mixed-precision path evaluates the same formula in single precision on 0.5 <= p < 5 with
-a shorter fit of g (unweighted: single-precision rounding dominates there).
+The mixed-precision path evaluates F1 and F2 in single precision from a table of cubics in q:
+0 <= q < 25 is cut into TAB32_N equal intervals, and on interval i, with the local variable
+x = q TAB32_N / 25 - i in [0, 1), F = c0 + x (c1 + x (c2 + x c3)), the interpolant at the four
+Chebyshev nodes of the interval of 40-digit values, rounded to single precision.  K1 = F1/delta
+and K2 = F2/delta^3 then take one table row, three fused multiply-adds per factor and no
+transcendental instruction; there is no cancellation anywhere in q.
 
 Run: python gen_smoothing.py  (rewrites sl_smoothing_coeffs.h next to this file and prints the
 achieved double-precision error of every approximation).
@@ -40,10 +44,10 @@ G_LO, G_HI = 1.0, 6.9   # range of the g fit (p)
 G_K = 3.0               # t = G_K / (G_K + p)
 G_DEG = 11
 EXP_DEG = 11            # degree of e^x on |x| <= ln2/2
-# Single-precision smoothing of the mixed path (0.5 <= p < 5): g as a polynomial in
-# t - G32_MID, t = G_K / (G_K + p), coefficients rounded to single precision.
-G32_LO, G32_HI = 0.5, 5.0
-G32_DEG = 7
+# Single-precision smoothing of the mixed path: cubics on TAB32_N equal intervals of
+# 0 <= q < TAB32_QMAX (p < 5, where s = 1 to single precision).
+TAB32_N = 256
+TAB32_QMAX = 25.0
 
 
 def cheb_nodes(a, b, n):
@@ -103,23 +107,40 @@ def exp_coeffs():
     return [c for c in mp.lu_solve(A, mp.matrix([mp.exp(x) for x in xs]))]
 
 
-def g32_coeffs():
-    ta, tb = G_K / (G_K + G32_HI), G_K / (G_K + G32_LO)
-    mid = float(np.float32((ta + tb) / 2))
-    nodes = [mp.cos(mp.pi * (j + mp.mpf(1) / 2) / (G32_DEG + 1)) for j in range(G32_DEG + 1)]
-    ts = [mp.mpf((ta + tb) / 2) + mp.mpf((tb - ta) / 2) * c for c in nodes]
-    A = mp.matrix([[(t - mp.mpf(mid)) ** i for i in range(G32_DEG + 1)] for t in ts])
-    y = mp.matrix([g_exact(G_K / t - G_K) for t in ts])
-    cf = [float(np.float32(float(c))) for c in mp.lu_solve(A, y)]
-    # error of the single-precision evaluation (numpy float32 mirrors the device arithmetic)
-    p = np.linspace(G32_LO, G32_HI, 2001)
-    t = (np.float32(G_K) * (np.float32(1) / (np.float32(G_K) + p.astype(np.float32)))).astype(np.float32)
-    t = (t - np.float32(mid)).astype(np.float32)
-    v = np.full_like(t, np.float32(cf[-1]))
-    for c in cf[-2::-1]:
-        v = (v * t + np.float32(c)).astype(np.float32)
-    err = max(float(abs(mp.mpf(float(a)) - g_exact(float(x)))) for x, a in zip(p[::4], v[::4]))
-    return cf, mid, err
+def tab32_coeffs():
+    """Per interval, the cubic in x in [0, 1) through F1, F2 at the interval's Chebyshev nodes."""
+    nodes = [(1 + mp.cos(mp.pi * (j + mp.mpf(1) / 2) / 4)) / 2 for j in range(4)]
+    A = mp.matrix([[x ** i for i in range(4)] for x in nodes])
+    h = mp.mpf(TAB32_QMAX) / TAB32_N
+    t1, t2 = [], []
+    for i in range(TAB32_N):
+        vals = [F_exact(h * (i + x)) for x in nodes]
+        c1 = mp.lu_solve(A, mp.matrix([v[0] for v in vals]))
+        c2 = mp.lu_solve(A, mp.matrix([v[1] for v in vals]))
+        t1.append([float(np.float32(float(c))) for c in c1])
+        t2.append([float(np.float32(float(c))) for c in c2])
+    return t1, t2
+
+
+def tab32_error(t1, t2):
+    """Max relative error of F1, F2 from the table, evaluated in single precision as on the
+    device (q rounded to single precision first; the error of that rounding is not counted)."""
+    f32 = np.float32
+    scale = f32(TAB32_N / TAB32_QMAX)
+    rng = np.random.default_rng(7)
+    qs = np.concatenate([np.linspace(0.0, TAB32_QMAX, 1201)[:-1],
+                         rng.uniform(0.0, TAB32_QMAX, 800)]).astype(np.float32)
+    worst = [0.0, 0.0]
+    for q in qs:
+        u = min(f32(q * scale), f32(np.nextafter(f32(TAB32_N), f32(0))))
+        i = int(u)
+        x = f32(u - f32(i))
+        ex = F_exact(float(q))
+        for k, tab in enumerate((t1, t2)):
+            c = [f32(v) for v in tab[i]]
+            v = f32(f32(f32(f32(f32(c[3] * x) + c[2]) * x) + c[1]) * x + c[0])
+            worst[k] = max(worst[k], float(abs(mp.mpf(float(v)) - ex[k]) / ex[k]))
+    return worst
 
 
 def horner(cf, x):
@@ -191,8 +212,8 @@ def main():
     ec = exp_coeffs()
     hi, lo = ln2_split()
     rep = check(c1, c2, gc, ec)
-    g32, g32_mid, g32_err = g32_coeffs()
-    rep["g32_abs"] = g32_err
+    t1, t2 = tab32_coeffs()
+    rep["tab32_rel_F1"], rep["tab32_rel_F2"] = tab32_error(t1, t2)
     for k, v in rep.items():
         print(f"{k}: {v:.3e}")
     lines = [
@@ -221,11 +242,14 @@ def main():
         f"constexpr double kLn2Hi = {hi!r};",
         f"constexpr double kLn2Lo = {lo!r};",
         f"constexpr double kLog2E = {float(1 / mp.log(2))!r};",
-        f"// single precision (mixed path), 0.5 <= p < 5, g abs error {g32_err:.2e}:",
-        f"// g(p) ~= sum kG32[i] (t - kG32Mid)^i, t = kGK / (kGK + p)",
-        f"constexpr int kG32Deg = {G32_DEG};",
-        f"constexpr float kG32Mid = {g32_mid!r}f;",
-        "constexpr float kG32[kG32Deg + 1] = {" + ", ".join(f"{c:.9e}f" for c in g32) + "};",
+        "// Single precision (mixed path), 0 <= q < kTab32QMax: interval i = floor(x'), x' = q kTab32N /",
+        "// kTab32QMax, x = x' - i; F1 ~= c0 + x (c1 + x (c2 + x c3)) with c = kTab32[i][0..3], F2 likewise",
+        f"// from kTab32[kTab32N + i].  Max relative error F1 {rep['tab32_rel_F1']:.2e}, F2 {rep['tab32_rel_F2']:.2e}.",
+        f"constexpr int kTab32N = {TAB32_N};",
+        f"constexpr float kTab32QMax = {TAB32_QMAX!r}f;",
+        "constexpr float kTab32[2 * kTab32N][4] = {",
+        *["    {" + ", ".join(f"{c:.9e}f" for c in row) + "}," for row in t1 + t2],
+        "};",
         "}  // namespace sl",
         "",
     ]

@@ -291,41 +291,47 @@ __device__ __forceinline__ void zone_pair64(double tx, double ty, double tz,
     az = fma(K1, gz, fma(c, dz, az));
 }
 
-// Single-precision constants of the mixed path's near zone for one target: 1/delta, 1/delta^2,
-// and the squared radii of its double-precision zone (rho64 delta)^2 and of the smoothing
-// (5 delta)^2.
+// Single-precision constants of the mixed path's near zone for one target: 1/delta, 1/delta^3,
+// the table scale kTab32N / (kTab32QMax delta^2) (table position of r^2), and the squared radii
+// of its double-precision zone (rho64 delta)^2 and of the smoothing (5 delta)^2.
 struct DeltaC32 {
-    float id, id2, cut2_64, cut2_5;
+    float id, id3, tsc, cut2_64, cut2_5;
 };
 
 __device__ __forceinline__ DeltaC32 make_delta32(double delta, double rho64)
 {
     DeltaC32 c;
     c.id = (float)(1.0 / delta);
-    c.id2 = (float)(1.0 / (delta * delta));
+    c.id3 = (float)(1.0 / (delta * delta * delta));
+    c.tsc = (float)((double)kTab32N / ((double)kTab32QMax * delta * delta));
     c.cut2_64 = (float)(rho64 * rho64 * delta * delta);
     c.cut2_5 = (float)(kRhoExact32 * kRhoExact32 * delta * delta);
     return c;
 }
 
-// Smoothed K1 = s1(p)/r, K2 = s2(p)/r^3 in single precision for 0.5 <= p < 5 (no cancellation
-// there: s1 >= 1.5 p, s2 >= 0.55): s = 1 - e^{-q} (g(p) + P(p)) as in smoothing_large64, with the
-// hardware exp2 and reciprocal and a degree-7 fit of g.
-__device__ __forceinline__ void smoothing32(float r2, float ri, const DeltaC32 &dc, float &K1,
-                                            float &K2)
+// The single-precision smoothing table (F1 rows, then F2 rows; four cubic coefficients a row),
+// copied into LDS by the threads of a workgroup.  The caller synchronizes afterwards.
+constexpr int kTab32Rows = 2 * kTab32N;
+
+__device__ __forceinline__ void load_tab32(float4 *tab)
 {
-    const float q = r2 * dc.id2;
-    const float p = (r2 * ri) * dc.id;
-    const float E = __builtin_amdgcn_exp2f(-q * 1.44269504088896340736f);
-    const float t = (float)kGK * __builtin_amdgcn_rcpf((float)kGK + p) - kG32Mid;
-    float g = kG32[kG32Deg];
-#pragma unroll
-    for (int i = kG32Deg - 1; i >= 0; --i) g = fmaf(g, t, kG32[i]);
-    const float c0p = (float)kC0 * p;
-    const float A1 = fmaf(c0p, fmaf(2.0f, q, -5.0f), g);
-    const float A2 = fmaf(c0p, fmaf(q, fmaf(4.0f, q, -14.0f), 3.0f), g);
-    K1 = ri * fmaf(-E, A1, 1.0f);
-    K2 = (ri * ri * ri) * fmaf(-E, A2, 1.0f);
+    for (int i = threadIdx.x; i < kTab32Rows; i += blockDim.x)
+        tab[i] = make_float4(kTab32[i][0], kTab32[i][1], kTab32[i][2], kTab32[i][3]);
+}
+
+// Smoothed K1 = s1(p)/r = F1(q)/delta and K2 = s2(p)/r^3 = F2(q)/delta^3 in single precision,
+// q = (r/delta)^2 < 25, from the table of cubics (no transcendental instruction, no cancellation).
+// Positions beyond the table are clamped to its last interval; the caller selects those lanes out.
+__device__ __forceinline__ void smoothing32(float r2, const DeltaC32 &dc, const float4 *tab,
+                                            float &K1, float &K2)
+{
+    const float u = fminf(r2 * dc.tsc, (float)kTab32N - 0x1p-16f);
+    const int i = (int)u;
+    const float x = u - (float)i;
+    const float4 a = tab[i];
+    const float4 b = tab[kTab32N + i];
+    K1 = fmaf(fmaf(fmaf(a.w, x, a.z), x, a.y), x, a.x) * dc.id;
+    K2 = fmaf(fmaf(fmaf(b.w, x, b.z), x, b.y), x, b.x) * dc.id3;
 }
 
 // Near pair of the mixed path.  p < rho64 (including r = 0): the double-precision kernel,
@@ -333,14 +339,16 @@ __device__ __forceinline__ void smoothing32(float r2, float ri, const DeltaC32 &
 // plain Stokeslet in single precision; both accumulated in (px, py, pz).  The zone is decided
 // from the single-precision distance.  The smoothing and the double-precision zone run only when
 // some lane of the wavefront needs them (wave-uniform tests), so a source that is farther than
-// 5 delta from all 64 targets of the wavefront costs what a far pair costs.
+// 5 delta from all 64 targets of the wavefront costs what a far pair costs.  `tab` is the
+// single-precision smoothing table (load_tab32).
 __device__ __forceinline__ void near_pair_mixed(float tx32, float ty32, float tz32, double tx,
                                                 double ty, double tz, float sx32, float sy32,
                                                 float sz32, float gx32, float gy32, float gz32,
                                                 double sx, double sy, double sz, double gx,
                                                 double gy, double gz, const DeltaC &dc64,
-                                                const DeltaC32 &dc32, float &px, float &py,
-                                                float &pz, double &ax, double &ay, double &az)
+                                                const DeltaC32 &dc32, const float4 *tab,
+                                                float &px, float &py, float &pz, double &ax,
+                                                double &ay, double &az)
 {
     const float dx = tx32 - sx32, dy = ty32 - sy32, dz = tz32 - sz32;
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
@@ -350,7 +358,7 @@ __device__ __forceinline__ void near_pair_mixed(float tx32, float ty32, float tz
     float K1 = ri, K2 = ri * ri * ri;
     if (__builtin_amdgcn_ballot_w64(z5)) {
         float S1, S2;
-        smoothing32(r2, ri, dc32, S1, S2);
+        smoothing32(r2, dc32, tab, S1, S2);
         K1 = z5 ? S1 : K1;
         K2 = z5 ? S2 : K2;
     }

@@ -172,7 +172,8 @@ __device__ __forceinline__ void far_cluster(const Src &S, int64_t j0, Acc<R, VAR
 // two-sum pair, as for far clusters.
 template <int R, bool VARD, bool MIXED>
 __device__ __forceinline__ void near_cluster(const Src &S, int64_t j0, const DeltaC &dcu,
-                                             const DeltaC32 &dcu32, Acc<R, VARD, MIXED> &A)
+                                             const DeltaC32 &dcu32, const float4 *tab,
+                                             Acc<R, VARD, MIXED> &A)
 {
     if constexpr (MIXED) {
         float px[R], py[R], pz[R];
@@ -189,7 +190,7 @@ __device__ __forceinline__ void near_cluster(const Src &S, int64_t j0, const Del
                 near_pair_mixed(A.tx32[r], A.ty32[r], A.tz32[r], A.tx[r], A.ty[r], A.tz[r], sx32,
                                 sy32, sz32, gx32, gy32, gz32, sx, sy, sz, gx, gy, gz,
                                 VARD ? A.dc[VARD ? r : 0] : dcu, VARD ? A.dc32[VARD ? r : 0] : dcu32,
-                                px[r], py[r], pz[r], A.ax[r], A.ay[r], A.az[r]);
+                                tab, px[r], py[r], pz[r], A.ax[r], A.ay[r], A.az[r]);
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -224,7 +225,7 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
 template <int R, bool VARD, bool MIXED>
 __device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec &rec,
                                           const TBlockRec &own, bool grouped, const Src &S,
-                                          const double4 *__restrict__ sphere,
+                                          const double4 *__restrict__ sphere, const float4 *tab,
                                           double *__restrict__ part, int tb, int k)
 {
     const uint32_t K = (uint32_t)a.n_ways;
@@ -276,7 +277,7 @@ __device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec &re
             if (((mf >> b) & 1) || (grouped && cluster_is_far(own, sphere[c0 + b])))
                 far_cluster<R, VARD, MIXED>(S, j0, A);
             else
-                near_cluster<R, VARD, MIXED>(S, j0, dcu, dcu32, A);
+                near_cluster<R, VARD, MIXED>(S, j0, dcu, dcu32, tab, A);
         }
     }
 
@@ -310,6 +311,9 @@ __global__ __launch_bounds__(G * kWave) void k_pair(PairArgs a, const TBlockRec 
                                                     uint32_t *__restrict__ ctr)
 {
     __shared__ uint32_t sh_item;
+    // Single-precision smoothing table; the first barrier of the work loop publishes it.
+    __shared__ float4 sh_tab[MIXED ? kTab32Rows : 1];
+    if constexpr (MIXED) load_tab32(sh_tab);
     const Src S{Sd, Sf};
     const uint32_t K = (uint32_t)a.n_ways;
     const int n_groups = (a.n_tblocks + G - 1) / G;
@@ -325,7 +329,7 @@ __global__ __launch_bounds__(G * kWave) void k_pair(PairArgs a, const TBlockRec 
         const int tb = g * G + w;
         if (tb < a.n_tblocks)
             pair_item<R, VARD, MIXED>(a, recs[g], recs[G > 1 ? n_groups + tb : g], G > 1, S, sphere,
-                                      part, tb, (int)(item % K));
+                                      sh_tab, part, tb, (int)(item % K));
     }
 }
 

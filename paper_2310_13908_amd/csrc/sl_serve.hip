@@ -185,7 +185,7 @@ __device__ void run_gather(const ServeArgs &a, const WorkItem &it)
                                __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ void run_pair(const ServeArgs &a, const WorkItem &it)
+__device__ void run_pair(const ServeArgs &a, const WorkItem &it, const float4 *tab)
 {
     constexpr int R = kServeR;
     const int lane = threadIdx.x;
@@ -304,8 +304,8 @@ __device__ void run_pair(const ServeArgs &a, const WorkItem &it)
 #pragma unroll
                     for (int r = 0; r < R; ++r)
                         near_pair_mixed(tx32[r], ty32[r], tz32[r], tx[r], ty[r], tz[r], f0, f1, f2,
-                                        h0, h1, h2, s0, s1, s2, g0, g1, g2, dc, dc32, px[r], py[r],
-                                        pz[r], ax[r], ay[r], az[r]);
+                                        h0, h1, h2, s0, s1, s2, g0, g1, g2, dc, dc32, tab, px[r],
+                                        py[r], pz[r], ax[r], ay[r], az[r]);
                 }
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
@@ -351,6 +351,9 @@ __device__ void run_pair(const ServeArgs &a, const WorkItem &it)
 
 __global__ __launch_bounds__(kWave) void k_serve(ServeArgs a)
 {
+    __shared__ float4 sh_tab[kTab32Rows];   // single-precision smoothing table
+    load_tab32(sh_tab);
+    __syncthreads();
     const int lane = threadIdx.x;
     if (lane == 0) {
         // The first wave of this launch starts the idle clock; later-starting waves must not
@@ -429,7 +432,7 @@ __global__ __launch_bounds__(kWave) void k_serve(ServeArgs a)
         if (it.kind == kItemGather)
             run_gather(a, it);
         else
-            run_pair(a, it);
+            run_pair(a, it, sh_tab);
     }
 }
 

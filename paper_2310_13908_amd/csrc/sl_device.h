@@ -334,24 +334,31 @@ __device__ __forceinline__ void smoothing32(float r2, const DeltaC32 &dc, const 
     K2 = fmaf(fmaf(fmaf(b.w, x, b.z), x, b.y), x, b.x) * dc.id3;
 }
 
-// Near pair of the mixed path.  p < rho64 (including r = 0): the double-precision kernel,
-// accumulated in (ax, ay, az).  rho64 <= p < 5: smoothed kernel in single precision; p >= 5:
-// plain Stokeslet in single precision; both accumulated in (px, py, pz).  The zone is decided
-// from the single-precision distance.  The smoothing and the double-precision zone run only when
-// some lane of the wavefront needs them (wave-uniform tests), so a source that is farther than
-// 5 delta from all 64 targets of the wavefront costs what a far pair costs.  `tab` is the
-// single-precision smoothing table (load_tab32).
-__device__ __forceinline__ void near_pair_mixed(float tx32, float ty32, float tz32, double tx,
-                                                double ty, double tz, float sx32, float sy32,
-                                                float sz32, float gx32, float gy32, float gz32,
-                                                double sx, double sy, double sz, double gx,
-                                                double gy, double gz, const DeltaC &dc64,
-                                                const DeltaC32 &dc32, const float4 *tab,
-                                                float &px, float &py, float &pz, double &ax,
-                                                double &ay, double &az)
+// Difference and squared distance in single precision for the mixed path.  Every kernel takes
+// them from here, so a pair falls in the same zone (double-precision zone, smoothing, plain) in
+// every kernel that looks at it.
+__device__ __forceinline__ float diff32(float tx, float ty, float tz, float sx, float sy, float sz,
+                                        float &dx, float &dy, float &dz)
 {
-    const float dx = tx32 - sx32, dy = ty32 - sy32, dz = tz32 - sz32;
-    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    dx = tx - sx;
+    dy = ty - sy;
+    dz = tz - sz;
+    return fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+}
+
+// Near pair of the mixed path, single-precision zones: rho64 <= p < 5 smoothed, p >= 5 plain,
+// accumulated in (px, py, pz); p < rho64 (including r = 0) contributes nothing here -- that zone
+// is summed in double precision by zone_pair_mixed.  The smoothing runs only when some lane of
+// the wavefront needs it (a wave-uniform test), so a source that is farther than 5 delta from
+// all 64 targets of the wavefront costs what a far pair costs.  `tab` is the single-precision
+// smoothing table (load_tab32).
+__device__ __forceinline__ void near_pair32(float tx32, float ty32, float tz32, float sx32,
+                                            float sy32, float sz32, float gx32, float gy32,
+                                            float gz32, const DeltaC32 &dc32, const float4 *tab,
+                                            float &px, float &py, float &pz)
+{
+    float dx, dy, dz;
+    const float r2 = diff32(tx32, ty32, tz32, sx32, sy32, sz32, dx, dy, dz);
     const bool z64 = r2 < dc32.cut2_64;
     const bool z5 = r2 < dc32.cut2_5;
     const float ri = __builtin_amdgcn_rsqf(r2);
@@ -364,14 +371,48 @@ __device__ __forceinline__ void near_pair_mixed(float tx32, float ty32, float tz
     }
     K1 = z64 ? 0.0f : K1;
     K2 = z64 ? 0.0f : K2;
-    if (__builtin_amdgcn_ballot_w64(z64)) {
-        if (z64) zone_pair64(tx, ty, tz, sx, sy, sz, gx, gy, gz, dc64, ax, ay, az);
-    }
     const float gd = fmaf(gx32, dx, fmaf(gy32, dy, gz32 * dz));
     const float c = gd * K2;
     px = fmaf(K1, gx32, fmaf(c, dx, px));
     py = fmaf(K1, gy32, fmaf(c, dy, py));
     pz = fmaf(K1, gz32, fmaf(c, dz, pz));
+}
+
+// The mixed path's double-precision zone: the pairs that near_pair32 leaves out (single-
+// precision distance below rho64 delta: the self term and the nearest neighbours, where the
+// difference of the positions cancels), in double precision, accumulated in (ax, ay, az).  The
+// source's double-precision record `e` (x, y, z, gx, gy, gz) is read only when some lane of the
+// wavefront has such a pair.
+__device__ __forceinline__ void zone_pair_mixed(float tx32, float ty32, float tz32, double tx,
+                                                double ty, double tz, float sx32, float sy32,
+                                                float sz32, const double *__restrict__ e,
+                                                const DeltaC &dc64, const DeltaC32 &dc32,
+                                                double &ax, double &ay, double &az)
+{
+    float dx, dy, dz;
+    const bool z64 = diff32(tx32, ty32, tz32, sx32, sy32, sz32, dx, dy, dz) < dc32.cut2_64;
+    if (__builtin_amdgcn_ballot_w64(z64)) {
+        const double sx = e[0], sy = e[1], sz = e[2], gx = e[3], gy = e[4], gz = e[5];
+        if (z64) zone_pair64(tx, ty, tz, sx, sy, sz, gx, gy, gz, dc64, ax, ay, az);
+    }
+}
+
+// Both zones of the mixed path for one pair (the serving kernel's near pair).
+__device__ __forceinline__ void near_pair_mixed(float tx32, float ty32, float tz32, double tx,
+                                                double ty, double tz, float sx32, float sy32,
+                                                float sz32, float gx32, float gy32, float gz32,
+                                                double sx, double sy, double sz, double gx,
+                                                double gy, double gz, const DeltaC &dc64,
+                                                const DeltaC32 &dc32, const float4 *tab,
+                                                float &px, float &py, float &pz, double &ax,
+                                                double &ay, double &az)
+{
+    near_pair32(tx32, ty32, tz32, sx32, sy32, sz32, gx32, gy32, gz32, dc32, tab, px, py, pz);
+    float dx, dy, dz;
+    const bool z64 = diff32(tx32, ty32, tz32, sx32, sy32, sz32, dx, dy, dz) < dc32.cut2_64;
+    if (__builtin_amdgcn_ballot_w64(z64)) {
+        if (z64) zone_pair64(tx, ty, tz, sx, sy, sz, gx, gy, gz, dc64, ax, ay, az);
+    }
 }
 
 // Plain Stokeslet pair in single precision (far zone of the mixed path).

@@ -167,12 +167,15 @@ __device__ __forceinline__ void far_cluster(const Src &S, int64_t j0, Acc<R, VAR
     }
 }
 
-// FP64 path: every pair in double precision.  Mixed path: near_pair_mixed (double precision
-// only below rho64 delta); single-precision terms are summed per cluster and folded into the
-// two-sum pair, as for far clusters.
+// FP64 path: every pair in double precision.  Mixed path: near_pair32 (the single-precision
+// zones), summed per cluster and folded into the two-sum pair as for far clusters, and the
+// double-precision zone (the self term and the nearest neighbours) as in zone_pair_mixed, whose
+// state lives in LDS (`zs`: per target of the lane, x, y, z and the three sums, 64 apart): it is
+// needed only for the few sources with such a pair, and keeping it out of the vector registers
+// buys the kernel two more waves per SIMD.
 template <int R, bool VARD, bool MIXED>
 __device__ __forceinline__ void near_cluster(const Src &S, int64_t j0, const DeltaC &dcu,
-                                             const DeltaC32 &dcu32, const float4 *tab,
+                                             const DeltaC32 &dcu32, const float4 *tab, double *zs,
                                              Acc<R, VARD, MIXED> &A)
 {
     if constexpr (MIXED) {
@@ -183,14 +186,32 @@ __device__ __forceinline__ void near_cluster(const Src &S, int64_t j0, const Del
         for (int j = 0; j < kCluster; ++j) {
             const float *q = S.f + (j0 + j) * 8;
             const float sx32 = q[0], sy32 = q[1], sz32 = q[2], gx32 = q[3], gy32 = q[4], gz32 = q[5];
-            const double *e = S.d + (j0 + j) * 8;
-            const double sx = e[0], sy = e[1], sz = e[2], gx = e[3], gy = e[4], gz = e[5];
+            bool z64[R], any = false;
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-                near_pair_mixed(A.tx32[r], A.ty32[r], A.tz32[r], A.tx[r], A.ty[r], A.tz[r], sx32,
-                                sy32, sz32, gx32, gy32, gz32, sx, sy, sz, gx, gy, gz,
-                                VARD ? A.dc[VARD ? r : 0] : dcu, VARD ? A.dc32[VARD ? r : 0] : dcu32,
-                                tab, px[r], py[r], pz[r], A.ax[r], A.ay[r], A.az[r]);
+            for (int r = 0; r < R; ++r) {
+                const DeltaC32 &d32 = VARD ? A.dc32[VARD ? r : 0] : dcu32;
+                near_pair32(A.tx32[r], A.ty32[r], A.tz32[r], sx32, sy32, sz32, gx32, gy32, gz32, d32,
+                            tab, px[r], py[r], pz[r]);
+                float dx, dy, dz;
+                z64[r] = diff32(A.tx32[r], A.ty32[r], A.tz32[r], sx32, sy32, sz32, dx, dy, dz) < d32.cut2_64;
+                any = any || z64[r];
+            }
+            if (__builtin_amdgcn_ballot_w64(any)) {
+                const double *e = S.d + (j0 + j) * 8;
+                const double sx = e[0], sy = e[1], sz = e[2], gx = e[3], gy = e[4], gz = e[5];
+                const int lane = threadIdx.x % kWave;
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (z64[r]) {
+                        double *z = zs + r * 6 * kWave + lane;
+                        double ax = z[3 * kWave], ay = z[4 * kWave], az = z[5 * kWave];
+                        zone_pair64(z[0], z[kWave], z[2 * kWave], sx, sy, sz, gx, gy, gz,
+                                    VARD ? A.dc[VARD ? r : 0] : dcu, ax, ay, az);
+                        z[3 * kWave] = ax;
+                        z[4 * kWave] = ay;
+                        z[5 * kWave] = az;
+                    }
+            }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -226,7 +247,7 @@ template <int R, bool VARD, bool MIXED>
 __device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec &rec,
                                           const TBlockRec &own, bool grouped, const Src &S,
                                           const double4 *__restrict__ sphere, const float4 *tab,
-                                          double *__restrict__ part, int tb, int k)
+                                          double *zs, double *__restrict__ part, int tb, int k)
 {
     const uint32_t K = (uint32_t)a.n_ways;
     const int lane = threadIdx.x % kWave;
@@ -248,6 +269,11 @@ __device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec &re
             A.tx32[r] = a.t.x32[i];
             A.ty32[r] = a.t.y32[i];
             A.tz32[r] = a.t.z32[i];
+            double *z = zs + r * 6 * kWave + lane;
+            z[0] = A.tx[r];
+            z[kWave] = A.ty[r];
+            z[2 * kWave] = A.tz[r];
+            z[3 * kWave] = z[4 * kWave] = z[5 * kWave] = 0.0;
         }
         A.ax[r] = A.ay[r] = A.az[r] = 0.0;
         A.hx[r] = A.hy[r] = A.hz[r] = A.lx[r] = A.ly[r] = A.lz[r] = 0.0f;
@@ -277,7 +303,7 @@ __device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec &re
             if (((mf >> b) & 1) || (grouped && cluster_is_far(own, sphere[c0 + b])))
                 far_cluster<R, VARD, MIXED>(S, j0, A);
             else
-                near_cluster<R, VARD, MIXED>(S, j0, dcu, dcu32, tab, A);
+                near_cluster<R, VARD, MIXED>(S, j0, dcu, dcu32, tab, zs, A);
         }
     }
 
@@ -288,9 +314,10 @@ __device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec &re
     for (int r = 0; r < R; ++r) {
         const int64_t i = t0 + r * kWave + lane;
         if constexpr (MIXED) {
-            px[i] = A.ax[r] + ((double)A.hx[r] + (double)A.lx[r]);
-            py[i] = A.ay[r] + ((double)A.hy[r] + (double)A.ly[r]);
-            pz[i] = A.az[r] + ((double)A.hz[r] + (double)A.lz[r]);
+            const double *z = zs + r * 6 * kWave + lane;
+            px[i] = z[3 * kWave] + ((double)A.hx[r] + (double)A.lx[r]);
+            py[i] = z[4 * kWave] + ((double)A.hy[r] + (double)A.ly[r]);
+            pz[i] = z[5 * kWave] + ((double)A.hz[r] + (double)A.lz[r]);
         } else {
             px[i] = A.ax[r];
             py[i] = A.ay[r];
@@ -314,6 +341,8 @@ __global__ __launch_bounds__(G * kWave) void k_pair(PairArgs a, const TBlockRec 
     // Single-precision smoothing table; the first barrier of the work loop publishes it.
     __shared__ float4 sh_tab[MIXED ? kTab32Rows : 1];
     if constexpr (MIXED) load_tab32(sh_tab);
+    // Mixed path: the double-precision zone's per-target state, R * 6 * 64 doubles per wave.
+    __shared__ double sh_zone[MIXED ? G * R * 6 * kWave : 1];
     const Src S{Sd, Sf};
     const uint32_t K = (uint32_t)a.n_ways;
     const int n_groups = (a.n_tblocks + G - 1) / G;
@@ -329,7 +358,8 @@ __global__ __launch_bounds__(G * kWave) void k_pair(PairArgs a, const TBlockRec 
         const int tb = g * G + w;
         if (tb < a.n_tblocks)
             pair_item<R, VARD, MIXED>(a, recs[g], recs[G > 1 ? n_groups + tb : g], G > 1, S, sphere,
-                                      sh_tab, part, tb, (int)(item % K));
+                                      sh_tab, sh_zone + (MIXED ? w * R * 6 * kWave : 0), part, tb,
+                                      (int)(item % K));
     }
 }
 

@@ -27,6 +27,7 @@ constexpr int kSortChunk = kSortThreads * kSortItems;   // elements per block an
 constexpr int kMortonBits = 8;                          // per axis
 constexpr int kDigitBits = 8;
 constexpr int kPasses = 3 * kMortonBits / kDigitBits;
+constexpr int kSortBlocksNoScan = 64;   // up to this many blocks, the scatters scan for themselves
 
 // ----------------------------------------------------------------------------------------
 // Bounding box
@@ -90,7 +91,7 @@ __device__ __forceinline__ uint32_t morton3(uint32_t qx, uint32_t qy, uint32_t q
     return k;
 }
 
-// Every block first folds the bounding-box partials (in the same order, so every block gets the
+// Clears the counts of sort passes 1 and 2.  Every block first folds the bounding-box partials (in the same order, so every block gets the
 // same box; block 0 also stores it with its centre for the later kernels).  Then: keys, identity
 // values, and the digit counts of the first sort pass (counts[digit * nblocks + block], block =
 // i / kSortChunk; integer atomics, so the counts do not depend on their order).
@@ -102,9 +103,17 @@ __global__ __launch_bounds__(256) void k_morton(const double *__restrict__ x,
                                                 double *__restrict__ centre_out,
                                                 uint32_t *__restrict__ keys,
                                                 uint32_t *__restrict__ vals,
-                                                uint32_t *__restrict__ counts, int nblocks)
+                                                uint32_t *__restrict__ counts, int nblocks,
+                                                uint32_t *__restrict__ clear1,
+                                                uint32_t *__restrict__ clear2, int64_t n_clear)
 {
     __shared__ double box[6];
+    // the counts of sort passes 1 and 2, accumulated by the scatters of passes 0 and 1
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_clear;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        clear1[i] = 0u;
+        clear2[i] = 0u;
+    }
     __shared__ double red[4][6];
     {   // one partial per thread (nparts <= 256), min / max over the block: order-independent
         double v[6];
@@ -174,17 +183,46 @@ __global__ __launch_bounds__(1024) void k_rs_scan(uint32_t *__restrict__ counts,
 }
 
 // Scatter by the digit at `shift`; when `next` is set, also counts the digit at shift + 8 of
-// every element for the block that owns its new position.
+// every element for the block that owns its new position.  `offs` holds the pass's counts,
+// exclusively scanned by k_rs_scan when `scanned`; otherwise (few blocks) every block takes its
+// offsets from the raw counts itself: for digit d, the counts of all digits below d plus those
+// of digit d in the blocks before it.
 __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n, int shift,
-    const uint32_t *__restrict__ offs, int nblocks, uint32_t *__restrict__ next)
+    const uint32_t *__restrict__ offs, int scanned, int nblocks, uint32_t *__restrict__ next,
+    uint32_t *__restrict__ clear)
 {
+    static_assert(kSortThreads == 256, "one thread per digit");
     constexpr int kWaves = kSortThreads / kWave;
     __shared__ uint32_t base[256];
     __shared__ uint32_t cnt[kWaves][256];
     const int t = threadIdx.x, w = t / kWave, lane = t % kWave;
-    base[t] = offs[(int64_t)t * nblocks + blockIdx.x];
+    if (clear)   // the first pass's counts, for a following sort
+        clear[(int64_t)t * nblocks + blockIdx.x] = 0u;
+    if (scanned) {
+        base[t] = offs[(int64_t)t * nblocks + blockIdx.x];
+    } else {
+        uint32_t row = 0, before = 0;
+        for (int b = 0; b < nblocks; ++b) {
+            const uint32_t c = offs[(int64_t)t * nblocks + b];
+            row += c;
+            before += b < (int)blockIdx.x ? c : 0u;
+        }
+        // exclusive scan of the digit totals: within each wave, then across the four waves
+        uint32_t incl = row;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint32_t v = __shfl_up(incl, o, kWave);
+            incl += lane >= o ? v : 0u;
+        }
+        if (lane == kWave - 1) cnt[0][w] = incl;
+        __syncthreads();
+        uint32_t wbase = 0;
+        for (int j = 0; j < w; ++j) wbase += cnt[0][j];
+        base[t] = wbase + incl - row + before;
+        __syncthreads();
+    }
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const int64_t start = (int64_t)blockIdx.x * kSortChunk;
     for (int k = 0; k < kSortItems; ++k) {
@@ -391,8 +429,10 @@ hipError_t launch_bbox(const double *ax, const double *ay, const double *az, int
     return hipGetLastError();
 }
 
-// Pass p scans counts[p] and clears counts[(p + 1) % 3] (the next pass's, and after the last
-// pass the first pass's of a following sort); its scatter counts into counts[p + 1].
+// k_morton counts pass 0's digits into counts[0] (cleared by k_bbox_partial) and clears
+// counts[1] and counts[2]; the scatter of pass p counts into counts[p + 1], and the last one
+// clears counts[0] for a following sort.  With more than kSortBlocksNoScan blocks, k_rs_scan
+// scans counts[p] before pass p (and clears counts[(p + 1) % 3] as well).
 hipError_t launch_sort_points(const double *x, const double *y, const double *z, int64_t n,
                               const PackScratch &ps, const uint32_t **order, hipStream_t st)
 {
@@ -400,14 +440,19 @@ hipError_t launch_sort_points(const double *x, const double *y, const double *z,
     const int64_t mb = (n + 255) / 256;
     hipLaunchKernelGGL(k_morton, dim3((unsigned)(mb < 1024 ? mb : 1024)), dim3(256), 0, st, x, y, z, n,
                        ps.bbox_part, ps.n_bbox_parts, ps.bbox, ps.centre, ps.keys[0], ps.vals[0],
-                       ps.counts[0], nb);
+                       ps.counts[0], nb, ps.counts[1], ps.counts[2], (int64_t)256 * nb);
+    // With few blocks every scatter block sums the raw counts itself (at most 64 per thread), and
+    // the single-workgroup scan launches are skipped.
+    const bool scan = nb > kSortBlocksNoScan;
     int cur = 0;
     for (int p = 0; p < kPasses; ++p) {
-        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, ps.counts[p], (int64_t)256 * nb,
-                           ps.counts[(p + 1) % 3]);
+        if (scan)
+            hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, ps.counts[p], (int64_t)256 * nb,
+                               ps.counts[(p + 1) % 3]);
         hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kSortThreads), 0, st, ps.keys[cur],
                            ps.vals[cur], ps.keys[cur ^ 1], ps.vals[cur ^ 1], n, p * kDigitBits,
-                           ps.counts[p], nb, p + 1 < kPasses ? ps.counts[p + 1] : nullptr);
+                           ps.counts[p], scan ? 1 : 0, nb, p + 1 < kPasses ? ps.counts[p + 1] : nullptr,
+                           p + 1 == kPasses ? ps.counts[0] : nullptr);
         cur ^= 1;
     }
     *order = ps.vals[cur];

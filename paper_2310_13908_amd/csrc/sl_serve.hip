@@ -43,6 +43,7 @@ constexpr int64_t kGatherChunk = 4096;           // points per gather item
 constexpr int kMaxSlots = 1024;                  // admitted requests in flight
 constexpr uint64_t kRingCap = 1ull << 21;        // work items in the ring (power of two)
 constexpr int kServeWavesPerSimd = 4;
+constexpr int kServeWaves = 4;                     // waves per workgroup (one smoothing table)
 constexpr double kIdleSeconds = 0.25;            // persistent kernel exits after this idle time
 constexpr double kGatherWaitSeconds = 2.0;       // bound on a pair item's wait for its gathers
 constexpr double kPollSeconds = 2e-6;            // spacing of the waves' host-memory polls
@@ -138,17 +139,6 @@ __device__ __forceinline__ T field(const T *p)
     memcpy(&out, &v, 8);
     return out;
 }
-__device__ __forceinline__ float bcast(float v, int j)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
-}
-__device__ __forceinline__ double bcast(double v, int j)
-{
-    const uint64_t b = (uint64_t)__double_as_longlong(v);
-    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, j);
-    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), j);
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
 __device__ __forceinline__ void idle_sleep(int rounds)
 {
     for (int k = 0; k < rounds; ++k) __builtin_amdgcn_s_sleep(127);
@@ -167,9 +157,9 @@ __device__ void run_gather(const ServeArgs &a, const WorkItem &it)
         static_assert(sizeof(ReqDesc) % 8 == 0, "descriptor copied in 8-byte words");
         const uint64_t *src = reinterpret_cast<const uint64_t *>(d);
         uint64_t *dst = reinterpret_cast<uint64_t *>(a.ddesc + it.slot);
-        for (int k = threadIdx.x; k < (int)(sizeof(ReqDesc) / 8); k += kWave) dst[k] = ld_sys(src + k);
+        for (int k = threadIdx.x % kWave; k < (int)(sizeof(ReqDesc) / 8); k += kWave) dst[k] = ld_sys(src + k);
     }
-    for (int64_t p = (int64_t)it.a + threadIdx.x; p < (int64_t)it.b; p += kWave) {
+    for (int64_t p = (int64_t)it.a + threadIdx.x % kWave; p < (int64_t)it.b; p += kWave) {
         const int32_t idx = perm[p];
         double vx = 0.0, vy = 0.0, vz = 0.0;
         if (idx >= 0) {
@@ -180,15 +170,25 @@ __device__ void run_gather(const ServeArgs &a, const WorkItem &it)
         if (mixed) { gx32[p] = (float)vx; gy32[p] = (float)vy; gz32[p] = (float)vz; }
     }
     __threadfence();
-    if (threadIdx.x == 0)
+    if (threadIdx.x % kWave == 0)
         __hip_atomic_fetch_add(&a.dc->gathers_done[it.slot], 1ull, __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ void run_pair(const ServeArgs &a, const WorkItem &it, const float4 *tab)
+// Per-wave LDS staging of one cluster's sources: 64 double-precision records (x, y, z, gx, gy, gz,
+// two spare) and 64 single-precision ones.  Each lane stores one source with coalesced loads; the
+// source loop then reads every record at one address across the wave (a broadcast), so the VALU
+// instructions take it as an ordinary vector operand.  A wave reads only what it wrote itself,
+// and LDS operations of one wave complete in order, so no barrier is needed.
+struct Stage {
+    double4 *d;   // [kCluster][2]
+    float4 *f;    // [kCluster][2]
+};
+
+__device__ void run_pair(const ServeArgs &a, const WorkItem &it, const float4 *tab, const Stage &st)
 {
     constexpr int R = kServeR;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x % kWave;
     const ReqDesc *d = a.desc + it.slot;
     // Wait until the request's density is packed.  Its gather items were claimed before this
     // item by running waves, so the wait ends; it is still bounded, and on expiry the item
@@ -257,19 +257,63 @@ __device__ void run_pair(const ServeArgs &a, const WorkItem &it, const float4 *t
     for (int64_t c = 0; c < n_cl; ++c) {
         const int64_t j0 = c * kCluster;
         const bool far = uni64(cluster_is_far(rec, sphere[c], gap_far) ? 1u : 0u) != 0;
+        // stage what this cluster's loop reads
+        if (mixed) {
+            st.f[2 * lane] = make_float4(sx32[j0 + lane], sy32[j0 + lane], sz32[j0 + lane], gx32[j0 + lane]);
+            st.f[2 * lane + 1] = make_float4(gy32[j0 + lane], gz32[j0 + lane], 0.0f, 0.0f);
+        }
+        if (!mixed || !far) {
+            st.d[2 * lane] = make_double4(sx[j0 + lane], sy[j0 + lane], sz[j0 + lane], gx[j0 + lane]);
+            st.d[2 * lane + 1] = make_double4(gy[j0 + lane], gz[j0 + lane], 0.0, 0.0);
+        }
         if (far && mixed) {
-            const float vx = sx32[j0 + lane], vy = sy32[j0 + lane], vz = sz32[j0 + lane];
-            const float wx = gx32[j0 + lane], wy = gy32[j0 + lane], wz = gz32[j0 + lane];
             float px[R], py[R], pz[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
 #pragma unroll 4
             for (int j = 0; j < kCluster; ++j) {
-                const float s0 = bcast(vx, j), s1 = bcast(vy, j), s2 = bcast(vz, j);
-                const float g0 = bcast(wx, j), g1 = bcast(wy, j), g2 = bcast(wz, j);
+                const float4 u = st.f[2 * j], v = st.f[2 * j + 1];
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    far_pair32(tx32[r], ty32[r], tz32[r], s0, s1, s2, g0, g1, g2, px[r], py[r], pz[r]);
+                    far_pair32(tx32[r], ty32[r], tz32[r], u.x, u.y, u.z, u.w, v.x, v.y, px[r], py[r], pz[r]);
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                two_sum_acc(px[r], hx[r], lx[r]);
+                two_sum_acc(py[r], hy[r], ly[r]);
+                two_sum_acc(pz[r], hz[r], lz[r]);
+            }
+        } else if (far) {
+#pragma unroll 2
+            for (int j = 0; j < kCluster; ++j) {
+                const double4 u = st.d[2 * j], v = st.d[2 * j + 1];
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    far_pair64(tx[r], ty[r], tz[r], u.x, u.y, u.z, u.w, v.x, v.y, ax[r], ay[r], az[r]);
+            }
+        } else if (mixed) {
+            float px[R], py[R], pz[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
+#pragma unroll 1
+            for (int j = 0; j < kCluster; ++j) {
+                const float4 u = st.f[2 * j], v = st.f[2 * j + 1];
+                bool z64[R], any = false;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    near_pair32(tx32[r], ty32[r], tz32[r], u.x, u.y, u.z, u.w, v.x, v.y, dc32, tab,
+                                px[r], py[r], pz[r]);
+                    float ex, ey, ez;
+                    z64[r] = diff32(tx32[r], ty32[r], tz32[r], u.x, u.y, u.z, ex, ey, ez) < dc32.cut2_64;
+                    any = any || z64[r];
+                }
+                if (__builtin_amdgcn_ballot_w64(any)) {
+                    const double4 U = st.d[2 * j], V = st.d[2 * j + 1];
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        if (z64[r]) zone_pair64(tx[r], ty[r], tz[r], U.x, U.y, U.z, U.w, V.x, V.y, dc,
+                                                ax[r], ay[r], az[r]);
+                }
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -278,50 +322,12 @@ __device__ void run_pair(const ServeArgs &a, const WorkItem &it, const float4 *t
                 two_sum_acc(pz[r], hz[r], lz[r]);
             }
         } else {
-            const double vx = sx[j0 + lane], vy = sy[j0 + lane], vz = sz[j0 + lane];
-            const double wx = gx[j0 + lane], wy = gy[j0 + lane], wz = gz[j0 + lane];
-            if (far) {
-#pragma unroll 2
-                for (int j = 0; j < kCluster; ++j) {
-                    const double s0 = bcast(vx, j), s1 = bcast(vy, j), s2 = bcast(vz, j);
-                    const double g0 = bcast(wx, j), g1 = bcast(wy, j), g2 = bcast(wz, j);
-#pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        far_pair64(tx[r], ty[r], tz[r], s0, s1, s2, g0, g1, g2, ax[r], ay[r], az[r]);
-                }
-            } else if (mixed) {
-                const float qx = sx32[j0 + lane], qy = sy32[j0 + lane], qz = sz32[j0 + lane];
-                const float ex = gx32[j0 + lane], ey = gy32[j0 + lane], ez = gz32[j0 + lane];
-                float px[R], py[R], pz[R];
-#pragma unroll
-                for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
 #pragma unroll 1
-                for (int j = 0; j < kCluster; ++j) {
-                    const double s0 = bcast(vx, j), s1 = bcast(vy, j), s2 = bcast(vz, j);
-                    const double g0 = bcast(wx, j), g1 = bcast(wy, j), g2 = bcast(wz, j);
-                    const float f0 = bcast(qx, j), f1 = bcast(qy, j), f2 = bcast(qz, j);
-                    const float h0 = bcast(ex, j), h1 = bcast(ey, j), h2 = bcast(ez, j);
+            for (int j = 0; j < kCluster; ++j) {
+                const double4 u = st.d[2 * j], v = st.d[2 * j + 1];
 #pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        near_pair_mixed(tx32[r], ty32[r], tz32[r], tx[r], ty[r], tz[r], f0, f1, f2,
-                                        h0, h1, h2, s0, s1, s2, g0, g1, g2, dc, dc32, tab, px[r],
-                                        py[r], pz[r], ax[r], ay[r], az[r]);
-                }
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    two_sum_acc(px[r], hx[r], lx[r]);
-                    two_sum_acc(py[r], hy[r], ly[r]);
-                    two_sum_acc(pz[r], hz[r], lz[r]);
-                }
-            } else {
-#pragma unroll 1
-                for (int j = 0; j < kCluster; ++j) {
-                    const double s0 = bcast(vx, j), s1 = bcast(vy, j), s2 = bcast(vz, j);
-                    const double g0 = bcast(wx, j), g1 = bcast(wy, j), g2 = bcast(wz, j);
-#pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        near_pair64(tx[r], ty[r], tz[r], s0, s1, s2, g0, g1, g2, dc, ax[r], ay[r], az[r]);
-                }
+                for (int r = 0; r < R; ++r)
+                    near_pair64(tx[r], ty[r], tz[r], u.x, u.y, u.z, u.w, v.x, v.y, dc, ax[r], ay[r], az[r]);
             }
         }
     }
@@ -349,12 +355,16 @@ __device__ void run_pair(const ServeArgs &a, const WorkItem &it, const float4 *t
     }
 }
 
-__global__ __launch_bounds__(kWave) void k_serve(ServeArgs a)
+__global__ __launch_bounds__(kServeWaves * kWave) void k_serve(ServeArgs a)
 {
-    __shared__ float4 sh_tab[kTab32Rows];   // single-precision smoothing table
+    __shared__ float4 sh_tab[kTab32Rows];   // single-precision smoothing table, shared
+    __shared__ double4 sh_d[kServeWaves][2 * kCluster];
+    __shared__ float4 sh_f[kServeWaves][2 * kCluster];
     load_tab32(sh_tab);
     __syncthreads();
-    const int lane = threadIdx.x;
+    // From here on every wave works on its own: it pulls its own items and leaves on its own.
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    const Stage stage{sh_d[wv], sh_f[wv]};
     if (lane == 0) {
         // The first wave of this launch starts the idle clock; later-starting waves must not
         // push it forward, or the kernel would outlive its idle limit.
@@ -432,7 +442,7 @@ __global__ __launch_bounds__(kWave) void k_serve(ServeArgs a)
         if (it.kind == kItemGather)
             run_gather(a, it);
         else
-            run_pair(a, it, sh_tab);
+            run_pair(a, it, sh_tab, stage);
     }
 }
 
@@ -821,13 +831,15 @@ sl_status Server::ensure_kernel_locked()
                 (uint64_t)(kPollSeconds * clock_hz) + 1, stats.kernel_launches + 1};
     // All waves resident at once (so that they share one idle clock), at most kServeWavesPerSimd
     // per SIMD.
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_serve, kWave, 0) != hipSuccess ||
+    int per_cu = 0;   // workgroups of kServeWaves waves
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_serve, kServeWaves * kWave, 0) !=
+            hipSuccess ||
         per_cu < 1)
-        per_cu = 4;
-    per_cu = per_cu < 4 * kServeWavesPerSimd ? per_cu : 4 * kServeWavesPerSimd;
+        per_cu = 1;
+    const int cap = 4 * kServeWavesPerSimd / kServeWaves;
+    per_cu = per_cu < cap ? per_cu : cap;
     const unsigned grid = (unsigned)(ctx->n_cu * per_cu);
-    hipLaunchKernelGGL(k_serve, dim3(grid), dim3(kWave), 0, kstream, a);
+    hipLaunchKernelGGL(k_serve, dim3(grid), dim3(kServeWaves * kWave), 0, kstream, a);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipEventRecord(kdone, kstream);
     if (e != hipSuccess) return hip_fail(e, "serving kernel launch");

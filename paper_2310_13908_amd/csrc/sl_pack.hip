@@ -204,6 +204,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(
         base[t] = offs[(int64_t)t * nblocks + blockIdx.x];
     } else {
         uint32_t row = 0, before = 0;
+#pragma unroll 16
         for (int b = 0; b < nblocks; ++b) {
             const uint32_t c = offs[(int64_t)t * nblocks + b];
             row += c;

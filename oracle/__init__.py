@@ -6,6 +6,8 @@ shares no code with it.  The arithmetic lives in ``slref.c`` (plain C, glibc
 erf/exp, Neumaier sums, OpenMP over targets); this module only builds and loads
 it and marshals numpy arrays.
 
+Also the per-patch regularization parameter of eq. (regparam) (``patch_delta``).
+
 Pinned by ``tests/test_oracle_pins.py`` against the r -> 0 limits stated in
 Sec. 3.4, vanishing moments of s - 1, the sphere's closed-form drag and
 rotation velocities, S[n] = 0 with the O(delta^5) order, the discrete
@@ -53,6 +55,8 @@ def _load():
         lib.slref_smoothing.restype = None
         lib.slref_kernel.argtypes = [d, d, P, P]
         lib.slref_kernel.restype = None
+        lib.slref_patch_delta.argtypes = [i64, i64, P, P, P, d, P]
+        lib.slref_patch_delta.restype = ctypes.c_int
         lib.slref_max_threads.argtypes = []
         lib.slref_max_threads.restype = ctypes.c_int
         _lib = lib
@@ -95,6 +99,22 @@ def single_layer(X, w, f, delta, mu=1.0, targets=None, delta_tgt=None, nthreads=
     if rc != 0:
         raise ValueError("slref_eval rejected its arguments")
     return np.stack([ux, uy, uz], axis=1)
+
+
+def patch_delta(X, n, C=1.0):
+    """Per-node delta = C delta*_i of eq. (regparam) for nodes X (6 n^2, 3) in patch-major,
+    row-major (l, l') order, n x n nodes per patch."""
+    lib = _load()
+    X = np.asarray(X, dtype=np.float64).reshape(-1, 3)
+    if n < 1 or X.shape[0] % (n * n) != 0:
+        raise ValueError("X must hold whole patches of n x n nodes")
+    n_patches = X.shape[0] // (n * n)
+    out = np.zeros(X.shape[0])
+    rc = lib.slref_patch_delta(n_patches, int(n), _ptr(_col(X[:, 0])), _ptr(_col(X[:, 1])),
+                               _ptr(_col(X[:, 2])), float(C), _ptr(out))
+    if rc != 0:
+        raise ValueError("slref_patch_delta rejected its arguments")
+    return out
 
 
 def smoothing(p: float):

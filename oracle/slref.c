@@ -126,3 +126,42 @@ int slref_max_threads(void)
     return 1;
 #endif
 }
+
+/*
+ * Per-patch regularization parameter, Sec. 3.4, eq. (regparam):
+ *
+ *   delta_{j,k}^{i} = C delta*_i,
+ *   delta*_i = max over the nodes X_{l,l'} of patch i of the largest Euclidean distance from
+ *              X_{l,l'} to its adjacent nodes X_{l-a,l'-b}, a, b in {-1, 0, 1}.
+ *
+ * Nodes are given patch-major, n x n per patch, (l, l') row-major (l, l' = 1..m-1, m = n + 1).
+ * Reading: the adjacent nodes are those of the patch's own grid, so a node on the edge of the
+ * grid has fewer neighbours (the grid of eq. (grid) has no nodes at l = 0 or m).  Every node of
+ * patch i receives C delta*_i.  Plain loops over the definition.
+ */
+int slref_patch_delta(int64_t n_patches, int64_t n, const double *x, const double *y,
+                      const double *z, double C, double *delta)
+{
+    if (n_patches < 1 || n < 1 || !(C > 0.0) || !isfinite(C)) return -1;
+    for (int64_t i = 0; i < n_patches; ++i) {
+        const int64_t base = i * n * n;
+        double dstar = 0.0;
+        for (int64_t l = 0; l < n; ++l)
+            for (int64_t lp = 0; lp < n; ++lp) {
+                const int64_t p = base + l * n + lp;
+                double de = 0.0;   /* d_e(X_{l,l'}, neighbours) */
+                for (int a = -1; a <= 1; ++a)
+                    for (int b = -1; b <= 1; ++b) {
+                        const int64_t ll = l - a, llp = lp - b;
+                        if (ll < 0 || ll >= n || llp < 0 || llp >= n) continue;
+                        const int64_t q = base + ll * n + llp;
+                        const double dx = x[p] - x[q], dy = y[p] - y[q], dz = z[p] - z[q];
+                        const double d = sqrt(dx * dx + dy * dy + dz * dz);
+                        if (d > de) de = d;
+                    }
+                if (de > dstar) dstar = de;
+            }
+        for (int64_t p = base; p < base + n * n; ++p) delta[p] = C * dstar;
+    }
+    return 0;
+}

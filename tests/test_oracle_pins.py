@@ -241,3 +241,66 @@ def test_brute_force_40_digits():
     ref = _brute_force_mp(s.X, s.w, f, d, 1.3)
     u = oracle.single_layer(s.X, s.w, f, d, mu=1.3)
     assert oracle.rel_inf_error(u, ref) < 5e-15
+
+
+# ---------------------------------------------------------------------------------------------
+# Per-patch regularization parameter delta = C delta* (Sec. 3.4, eq. (regparam))
+# ---------------------------------------------------------------------------------------------
+def planar_patch(n, fx, fy):
+    """Nodes (fx(l), fy(l'), 0) of one n x n patch, (l, l') row-major."""
+    l, lp = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    return np.stack([fx(l).ravel(), fy(lp).ravel(), np.zeros(n * n)], axis=1).astype(np.float64)
+
+
+def test_patch_delta_uniform_grid_is_the_diagonal():
+    """On a flat grid of spacings sx, sy the largest neighbour distance is the diagonal
+    sqrt(sx^2 + sy^2); every node of the patch gets C times it."""
+    import oracle
+    for n, sx, sy, C in ((2, 1.0, 1.0, 1.0), (5, 0.3, 0.4, 1.0), (7, 0.02, 0.05, 2.5)):
+        X = planar_patch(n, lambda l: sx * l, lambda lp: sy * lp)
+        d = oracle.patch_delta(X, n, C=C)
+        assert np.allclose(d, C * math.hypot(sx, sy), rtol=1e-15, atol=0)
+
+
+def test_patch_delta_stretched_grid():
+    """x = l^2, y = l': the widest cell is the last one, whose diagonal is sqrt((2n-3)^2 + 1)."""
+    import oracle
+    for n in (3, 6, 11):
+        X = planar_patch(n, lambda l: l.astype(np.float64) ** 2, lambda lp: lp.astype(np.float64))
+        assert np.allclose(oracle.patch_delta(X, n), math.hypot(2 * n - 3, 1.0), rtol=1e-15)
+
+
+def test_patch_delta_single_node_has_no_neighbours():
+    import oracle
+    assert np.all(oracle.patch_delta(np.array([[0.1, 0.2, 0.3]] * 6), 1) == 0.0)
+
+
+def test_patch_delta_per_patch_and_invariances():
+    """Each patch gets its own delta*; delta* scales with the surface and is invariant under a
+    rigid motion; on the 6-patch discretization it matches a brute force over all node pairs
+    of a patch that are adjacent in the grid."""
+    import oracle
+    n = 9
+    s = make_surface(RBC, n)
+    d = oracle.patch_delta(s.X, n)
+    per = d.reshape(6, n * n)
+    assert np.all(per == per[:, :1])                     # constant on each patch
+    l, lp = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    L, LP = l.ravel(), lp.ravel()
+    adj = (np.abs(L[:, None] - L[None]) <= 1) & (np.abs(LP[:, None] - LP[None]) <= 1)
+    for i in range(6):
+        P = s.X[i * n * n:(i + 1) * n * n]
+        dist = np.linalg.norm(P[:, None] - P[None], axis=-1)
+        assert per[i, 0] == pytest.approx(dist[adj].max(), rel=1e-15)
+    assert len(set(np.round(per[:, 0], 12))) > 1       # the RBC patches differ
+    assert np.allclose(oracle.patch_delta(3.0 * s.X, n), 3.0 * d, rtol=1e-14)
+    Q, _ = np.linalg.qr(np.random.default_rng(5).standard_normal((3, 3)))
+    assert np.allclose(oracle.patch_delta(s.X @ Q.T + [1.0, -2.0, 0.5], n), d, rtol=1e-13)
+
+
+def test_patch_delta_rejects_bad_arguments():
+    import oracle
+    with pytest.raises(ValueError):
+        oracle.patch_delta(np.zeros((10, 3)), 3)          # not whole patches
+    with pytest.raises(ValueError):
+        oracle.patch_delta(np.zeros((9, 3)), 3, C=0.0)

@@ -85,6 +85,55 @@ def measure_precision(ctx, P, prob, tens, precision, steps, warmup):
     return t * 1e3, kern_ms, out
 
 
+def resident(dev, X, w, f):
+    """Inputs resident in HBM in the library's structure-of-arrays layout: X and f are (N, 3)
+    views of contiguous (3, N) tensors, so the binding passes them without a copy."""
+    import numpy as np
+    import torch
+    soa = lambda a: torch.as_tensor(np.ascontiguousarray(np.asarray(a, dtype=np.float64).T), device=dev).t()
+    return soa(X), torch.as_tensor(np.asarray(w, dtype=np.float64), device=dev), soa(f)
+
+
+def patch_delta_leg(P, ctx, prob, tens, log, steps=20, warmup=3):
+    """The same C2 workload with the paper's default regularization, delta = C delta*_i per
+    patch (Sec. 3.4, eq. (regparam), C = 1): a step is the device pre-pass (sl_patch_delta)
+    plus sl_eval with the per-target delta; every target against the oracle with the oracle's
+    delta."""
+    import numpy as np
+    import torch
+    import oracle
+    X, w, F = tens
+    n = prob.surface.n
+    D = torch.empty(prob.N, dtype=torch.float64, device=X.device)
+    out = torch.empty((3, prob.N), dtype=torch.float64, device=X.device)
+    dref = oracle.patch_delta(prob.surface.X, n)
+    t0 = time.perf_counter()
+    ref = oracle.single_layer(prob.surface.X, prob.surface.w, prob.f, 0.0, delta_tgt=dref)
+    log(f"[bench] per-patch delta: oracle in {time.perf_counter() - t0:.1f} s")
+    per = dref.reshape(6, -1)[:, 0]
+    res = {"workload": "rbc_6x64x64_sh8, delta = delta*_i per patch (C = 1)",
+           "delta_star_min": float(per.min()), "delta_star_max": float(per.max()),
+           "delta_2h": prob.delta}
+    # the pre-pass alone
+    pre = time_steps(lambda: ctx.patch_delta(X, n, out=D), steps, warmup)
+    res["pre_pass_us"] = round(pre * 1e6, 2)
+    res["delta_bit_exact"] = bool(np.array_equal(D.cpu().numpy(), dref))
+    for prec in ("fp64", "mixed"):
+        def step():
+            ctx.patch_delta(X, n, out=D)
+            ctx.single_layer(X, w, F, 0.0, delta_tgt=D, precision=prec, out=out)
+        t = time_steps(step, steps, warmup)
+        e = rel_inf(out.t().cpu().numpy(), ref)
+        res[prec] = {"ms_per_step": round(t * 1e3, 4),
+                     "gpair_s": round(prob.N ** 2 / t / 1e9, 2), "eps_vs_oracle": e}
+        log(f"[bench] per-patch delta {prec}: {t * 1e3:.3f} ms/step  "
+            f"{res[prec]['gpair_s']:.0f} Gpair/s  eps {e:.2e}")
+    log(f"[bench] per-patch delta: pre-pass {res['pre_pass_us']:.1f} us, bit-exact "
+        f"{res['delta_bit_exact']}, delta* in [{res['delta_star_min']:.4g}, "
+        f"{res['delta_star_max']:.4g}] vs 2h = {prob.delta:.4g}")
+    return res
+
+
 def roofline(precision, pairs, near, kern_ms):
     flops = FLOPS_FAR * (pairs - near) + FLOPS_NEAR * near
     achieved = flops / (kern_ms * 1e-3) / 1e12
@@ -370,7 +419,7 @@ def main():
     dev = torch.device("cuda", 0)
     ctx = P.Context(0)
     prob = W.c2()
-    tens = tuple(torch.as_tensor(a, device=dev) for a in (prob.surface.X, prob.surface.w, prob.f))
+    tens = resident(dev, prob.surface.X, prob.surface.w, prob.f)
     pairs = prob.N * prob.N
     log(f"[bench] workload c2: RBC 6x64x64, N={prob.N}, delta={prob.delta:.6g}")
     near = count_near(tens[0], prob.delta, [RHO_EXACT64, 5.0])
@@ -413,8 +462,9 @@ def main():
 
     if not args.no_extras:
         import oracle
+        line["patch_delta"] = patch_delta_leg(P, ctx, prob, tens, log)
         p3 = W.c3()
-        t3 = tuple(torch.as_tensor(a, device=dev) for a in (p3.surface.X, p3.surface.w, p3.f))
+        t3 = resident(dev, p3.surface.X, p3.surface.w, p3.f)
         big = {"workload": "rbc_6x256x256_sh8", "N": p3.N}
         idx = W.c3_subset(p3.N, 256)
         ref3 = oracle.single_layer(p3.surface.X, p3.surface.w, p3.f, p3.delta,

@@ -115,6 +115,28 @@ sl_status sl_eval(sl_ctx *ctx, sl_precision prec,
                   double *ux, double *uy, double *uz, void *stream);
 
 /*
+ * Per-patch regularization parameter of Sec. 3.4, eq. (regparam), asynchronous on `stream`:
+ *
+ *   delta_out[p] = C delta*_i for every node p of patch i, where delta*_i is the largest
+ *   Euclidean distance between two nodes of patch i that are adjacent in its grid (row,
+ *   column or diagonal neighbours; an edge node has only the neighbours the grid holds).
+ *
+ *  x, y, z:    device arrays of n_patches n^2 nodes, patch-major and row-major within a patch
+ *              (the node order of the six-patch discretization, Sec. 3.2).
+ *  n_patches:  >= 1 (six for a closed surface); n >= 2 nodes per patch direction.
+ *  C:          the constant of eq. (regparam) (> 0, finite; the paper takes 1).
+ *  delta_out:  device array of n_patches n^2 doubles, overwritten; it must not overlap x, y, z.
+ *              Pass it as delta_tgt to sl_eval (targets = the same nodes).
+ *
+ * The result equals a plain double loop over the definition bit for bit (squared distances
+ * as ((dx dx + dy dy) + dz dz), maximum before the square root).  SL_EINVAL for bad sizes,
+ * C, NULL or overlapping arrays; SL_EHIP if the launch fails.
+ */
+sl_status sl_patch_delta(sl_ctx *ctx, int64_t n_patches, int64_t n, const double *x,
+                         const double *y, const double *z, double C, double *delta_out,
+                         void *stream);
+
+/*
  * Serving: device-resident surfaces and continuous batching.
  *
  * sl_surface_register copies n nodes (x, y, z, w: device arrays) into library-owned HBM,

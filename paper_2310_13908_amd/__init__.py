@@ -11,7 +11,7 @@ from . import _binding
 from ._binding import (EXPORTED, SL_EBUSY, SL_EHIP, SL_EINVAL, SL_ENOMEM, SL_ENOTFOUND, SL_ETIMEDOUT,
                        SL_FP64, SL_MIXED, SL_OK, SL_PARAM_KERNEL_TIMING, SL_PARAM_RHO64,
                        SL_PARAM_TARGETS_PER_LANE, SL_PARAM_WAVES_PER_SIMD, SlError, check, load, sl_create,
-                       sl_destroy, sl_eval, sl_get_param, sl_get_stats, sl_last_error, sl_poll,
+                       sl_destroy, sl_eval, sl_get_param, sl_get_stats, sl_last_error, sl_patch_delta, sl_poll,
                        sl_request_bytes, sl_set_param, sl_submit, sl_surface_register,
                        sl_surface_release, sl_wait)
 
@@ -83,6 +83,21 @@ class Context:
                      U[0].data_ptr(), U[1].data_ptr(), U[2].data_ptr(), _stream_handle(stream))
         check(st, "sl_eval")
         return U.t()
+
+    def patch_delta(self, X, n, C=1.0, stream=None, out=None):
+        """Per-node delta = C delta* of eq. (regparam) (float64 device tensor of X.shape[0])
+        for nodes X (n_patches n^2, 3) in patch-major, row-major order; enqueued on the current
+        torch stream (or `stream`).  Pass the result as `delta_tgt` to single_layer."""
+        import torch
+        Xs = _soa(X)
+        npts = Xs.shape[1]
+        if n < 1 or npts % (n * n) != 0:
+            raise ValueError("X must hold whole patches of n x n nodes")
+        D = out if out is not None else torch.empty(npts, dtype=torch.float64, device=Xs.device)
+        check(sl_patch_delta(self.ptr, npts // (n * n), int(n), Xs[0].data_ptr(), Xs[1].data_ptr(),
+                             Xs[2].data_ptr(), float(C), D.data_ptr(), _stream_handle(stream)),
+              "sl_patch_delta")
+        return D
 
     # -- serving ---------------------------------------------------------------------------
     def register_surface(self, X, w, delta) -> int:

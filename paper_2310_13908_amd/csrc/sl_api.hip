@@ -211,6 +211,29 @@ sl_status sl_get_stats(sl_ctx *ctx, sl_stats *out)
     return SL_OK;
 }
 
+sl_status sl_patch_delta(sl_ctx *ctx, int64_t n_patches, int64_t n, const double *x, const double *y,
+                         const double *z, double C, double *delta_out, void *stream)
+{
+    g_last_error.clear();
+    if (!ctx) return fail(SL_EINVAL, "sl_patch_delta: ctx is NULL");
+    if (n_patches < 1 || n < 2)
+        return fail(SL_EINVAL, "sl_patch_delta: need n_patches >= 1 and n >= 2 (a one-node patch has no neighbours)");
+    if (n > 32768 || n_patches > kMaxPoints / (n * n))
+        return fail(SL_EINVAL, "sl_patch_delta: more than 2^30 points");
+    if (!finite_pos(C)) return fail(SL_EINVAL, "sl_patch_delta: C must be finite and > 0");
+    if (!x || !y || !z || !delta_out) return fail(SL_EINVAL, "sl_patch_delta: NULL array");
+    const int64_t bytes = n_patches * n * n * 8;
+    const Range out{delta_out, bytes};
+    for (const void *in : {(const void *)x, (const void *)y, (const void *)z})
+        if (overlaps(out, Range{in, bytes}))
+            return fail(SL_EINVAL, "sl_patch_delta: delta_out aliases an input");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(SL_EHIP, "sl_patch_delta: hipSetDevice failed");
+    const hipError_t e = launch_patch_delta(n_patches, n, x, y, z, C, delta_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "sl_patch_delta: kernel launch");
+    return SL_OK;
+}
+
 sl_status sl_eval(sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *sx,
                   const double *sy, const double *sz, const double *w, const double *fx,
                   const double *fy, const double *fz, int64_t n_tgt, const double *tx,

@@ -100,6 +100,11 @@ hipError_t launch_reduce(const double *part, int n_ways, int64_t np, const int32
                          double scale, double *ux, double *uy, double *uz, hipStream_t st);
 hipError_t launch_fill_zero(double *ux, double *uy, double *uz, int64_t n, hipStream_t st);
 
+// Per-patch regularization parameter (sl_patch.hip): out[p] = C delta*_i for the n x n nodes
+// of each of n_patches patches (patch-major, row-major), n >= 1.
+hipError_t launch_patch_delta(int64_t n_patches, int64_t n, const double *x, const double *y,
+                              const double *z, double C, double *out, hipStream_t st);
+
 // ---------------------------------------------------------------------------------------
 // Packing: bounding box, Morton keys, stable radix sort, gather (sl_pack.hip)
 // ---------------------------------------------------------------------------------------

@@ -46,3 +46,5 @@ def test_host_side_validation_without_a_gpu():
     d = ctypes.c_double()
     assert lib.sl_get_param(None, P.SL_PARAM_RHO64, ctypes.byref(d)) == P.SL_EINVAL
     assert lib.sl_set_param(None, P.SL_PARAM_RHO64, 6.0) == P.SL_EINVAL
+    assert lib.sl_patch_delta(None, 6, 4, 1, 2, 3, 1.0, 4, None) == P.SL_EINVAL
+    assert "ctx is NULL" in P.sl_last_error()

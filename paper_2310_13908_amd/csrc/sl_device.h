@@ -347,11 +347,12 @@ __device__ __forceinline__ float diff32(float tx, float ty, float tz, float sx, 
 }
 
 // Near pair of the mixed path, single-precision zones: rho64 <= p < 5 smoothed, p >= 5 plain,
-// accumulated in (px, py, pz); p < rho64 (including r = 0) contributes nothing here -- that zone
-// is summed in double precision by zone_pair_mixed.  The smoothing runs only when some lane of
-// the wavefront needs it (a wave-uniform test), so a source that is farther than 5 delta from
-// all 64 targets of the wavefront costs what a far pair costs.  `tab` is the single-precision
-// smoothing table (load_tab32).
+// accumulated in (px, py, pz); p < rho64 (including r = 0) contributes nothing here -- the caller
+// sums that zone in double precision (zone_pair64), deciding it with the same diff32 test (the
+// self term and the nearest neighbours, where the difference of the positions cancels).  The
+// smoothing runs only when some lane of the wavefront needs it (a wave-uniform test), so a
+// source that is farther than 5 delta from all 64 targets of the wavefront costs what a far pair
+// costs.  `tab` is the single-precision smoothing table (load_tab32).
 __device__ __forceinline__ void near_pair32(float tx32, float ty32, float tz32, float sx32,
                                             float sy32, float sz32, float gx32, float gy32,
                                             float gz32, const DeltaC32 &dc32, const float4 *tab,
@@ -376,43 +377,6 @@ __device__ __forceinline__ void near_pair32(float tx32, float ty32, float tz32, 
     px = fmaf(K1, gx32, fmaf(c, dx, px));
     py = fmaf(K1, gy32, fmaf(c, dy, py));
     pz = fmaf(K1, gz32, fmaf(c, dz, pz));
-}
-
-// The mixed path's double-precision zone: the pairs that near_pair32 leaves out (single-
-// precision distance below rho64 delta: the self term and the nearest neighbours, where the
-// difference of the positions cancels), in double precision, accumulated in (ax, ay, az).  The
-// source's double-precision record `e` (x, y, z, gx, gy, gz) is read only when some lane of the
-// wavefront has such a pair.
-__device__ __forceinline__ void zone_pair_mixed(float tx32, float ty32, float tz32, double tx,
-                                                double ty, double tz, float sx32, float sy32,
-                                                float sz32, const double *__restrict__ e,
-                                                const DeltaC &dc64, const DeltaC32 &dc32,
-                                                double &ax, double &ay, double &az)
-{
-    float dx, dy, dz;
-    const bool z64 = diff32(tx32, ty32, tz32, sx32, sy32, sz32, dx, dy, dz) < dc32.cut2_64;
-    if (__builtin_amdgcn_ballot_w64(z64)) {
-        const double sx = e[0], sy = e[1], sz = e[2], gx = e[3], gy = e[4], gz = e[5];
-        if (z64) zone_pair64(tx, ty, tz, sx, sy, sz, gx, gy, gz, dc64, ax, ay, az);
-    }
-}
-
-// Both zones of the mixed path for one pair (the serving kernel's near pair).
-__device__ __forceinline__ void near_pair_mixed(float tx32, float ty32, float tz32, double tx,
-                                                double ty, double tz, float sx32, float sy32,
-                                                float sz32, float gx32, float gy32, float gz32,
-                                                double sx, double sy, double sz, double gx,
-                                                double gy, double gz, const DeltaC &dc64,
-                                                const DeltaC32 &dc32, const float4 *tab,
-                                                float &px, float &py, float &pz, double &ax,
-                                                double &ay, double &az)
-{
-    near_pair32(tx32, ty32, tz32, sx32, sy32, sz32, gx32, gy32, gz32, dc32, tab, px, py, pz);
-    float dx, dy, dz;
-    const bool z64 = diff32(tx32, ty32, tz32, sx32, sy32, sz32, dx, dy, dz) < dc32.cut2_64;
-    if (__builtin_amdgcn_ballot_w64(z64)) {
-        if (z64) zone_pair64(tx, ty, tz, sx, sy, sz, gx, gy, gz, dc64, ax, ay, az);
-    }
 }
 
 // Plain Stokeslet pair in single precision (far zone of the mixed path).

@@ -169,7 +169,7 @@ __device__ __forceinline__ void far_cluster(const Src &S, int64_t j0, Acc<R, VAR
 
 // FP64 path: every pair in double precision.  Mixed path: near_pair32 (the single-precision
 // zones), summed per cluster and folded into the two-sum pair as for far clusters, and the
-// double-precision zone (the self term and the nearest neighbours) as in zone_pair_mixed, whose
+// double-precision zone (the self term and the nearest neighbours, zone_pair64), whose
 // state lives in LDS (`zs`: per target of the lane, x, y, z and the three sums, 64 apart): it is
 // needed only for the few sources with such a pair, and keeping it out of the vector registers
 // buys the kernel two more waves per SIMD.

@@ -93,6 +93,26 @@ def test_c3_rbc_sampled(ctx, precision):
     assert np.all(np.isfinite(u))
 
 
+@pytest.mark.parametrize("n", [104, 105])
+def test_sort_paths_at_the_scan_threshold(ctx, n):
+    """N = 6 n^2 on either side of 64 sort blocks of 1024 keys (64,896 and 66,150 points): the
+    scatter passes take their offsets from the raw counts below it and from k_rs_scan above it.
+    Targets = sources and distinct targets (a second sort with the same scratch), 256 sampled
+    targets each against the oracle."""
+    import oracle
+    s = make_surface(RBC, n)
+    f = sh_force(s.x0, 300 + n)
+    d = 2 * math.pi / (n + 1)
+    idx = np.sort(np.random.default_rng(n).choice(s.N, size=256, replace=False))
+    for precision in ("fp64", "mixed"):
+        u = gpu_eval(ctx, s.X, s.w, f, d, precision=precision)
+        ref = oracle.single_layer(s.X, s.w, f, d, targets=s.X[idx])
+        assert eps(u[idx], ref) < TOL[precision]
+        T = s.X[idx] * 1.001
+        u = gpu_eval(ctx, s.X, s.w, f, d, targets=T, precision=precision)
+        assert eps(u, oracle.single_layer(s.X, s.w, f, d, targets=T)) < TOL[precision]
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_distinct_targets(ctx, precision):
     """Targets off the nodes: on-surface nodes, points near and far from the surface, and points

@@ -207,3 +207,35 @@ SPHERE = Shape("sphere")
 RBC = Shape("rbc")
 ELLIPSOID_SERVING = Shape("ellipsoid", (1.0, 0.8, 0.5))   # axes 1 : 0.8 : 0.5
 ELLIPSOID_PAPER = Shape("ellipsoid", (0.6, 1.0, 1.0))     # Sec. 4.1 test shape
+
+
+def fine_grid(n: int, factor: int = 4):
+    """Parameters of the upsampled grid of a patch with n x n nodes: factor * n nodes per
+    direction at j pi / (factor n + 1), j = 1..factor n (N_up = factor^2 N, the count of the
+    paper's upsampling table), and the coarse parameters j pi / (n + 1), j = 1..n."""
+    nf = factor * n
+    return (np.arange(1, n + 1) * np.pi / (n + 1), np.arange(1, nf + 1) * np.pi / (nf + 1))
+
+
+def fine_pou(n: int, factor: int = 4) -> np.ndarray:
+    """Own-patch POU values at the upsampled nodes (patch-major, row-major), eq. (pou) at the
+    sphere pre-images: the precomputed Psi_u of the upsampling step (Sec. 3.4)."""
+    _, tf = fine_grid(n, factor)
+    U, V = np.meshgrid(tf, tf, indexing="ij")
+    out = []
+    for i in range(1, N_PATCH + 1):
+        p, _, _ = chart(i, U, V)
+        out.append(pou(p)[i - 1].ravel())
+    return np.concatenate(out)
+
+
+def fine_positions(shape: "Shape", n: int, factor: int = 4) -> np.ndarray:
+    """Exact surface positions at the upsampled nodes (for checking interpolation only)."""
+    _, tf = fine_grid(n, factor)
+    U, V = np.meshgrid(tf, tf, indexing="ij")
+    out = []
+    for i in range(1, N_PATCH + 1):
+        p, _, _ = chart(i, U, V)
+        X, _ = shape.map(p)
+        out.append(X.reshape(3, -1).T)
+    return np.ascontiguousarray(np.concatenate(out))

@@ -117,6 +117,55 @@ def patch_delta(X, n, C=1.0):
     return out
 
 
+# ----------------------------------------------------------------------------------------------
+# Upsampling sandwich (Sec. 3.4, "Upsampling"): u = I_d S^{delta_u}[I_u f] on I_u X.
+# Readings: the fine grid has factor*n nodes per direction at j pi/(factor n + 1) (N_up =
+# factor^2 N, the count of the paper's table); I_u and I_d are per-patch tensor-product cubic
+# splines with not-a-knot ends (de Boor's default), the end pieces extended where the fine grid
+# reaches past the coarse nodes; the fine weights are psi_u W_u h_u^2 with W_u = |X_u x X_v| from
+# the splines' derivatives; delta_u is eq. (regparam) on the fine grid.
+# ----------------------------------------------------------------------------------------------
+def _grids(n, factor):
+    nf = factor * n
+    return np.arange(1, n + 1) * np.pi / (n + 1), np.arange(1, nf + 1) * np.pi / (nf + 1)
+
+
+def spline_resample(F, n_from, t_from, t_to, du=0, dv=0):
+    """Per patch, the tensor-product not-a-knot cubic spline through values F on the grid
+    t_from x t_from (patch-major, row-major, trailing components allowed), evaluated (or its
+    du-th u- and dv-th v-derivative) on t_to x t_to."""
+    from scipy.interpolate import CubicSpline
+    F = np.asarray(F, dtype=np.float64)
+    comp = F.shape[1:]
+    G = F.reshape((-1, n_from, n_from) + comp)
+    a = CubicSpline(t_from, G, axis=1, bc_type="not-a-knot", extrapolate=True)
+    G = a(t_to, du) if du else a(t_to)
+    b = CubicSpline(t_from, G, axis=2, bc_type="not-a-knot", extrapolate=True)
+    G = b(t_to, dv) if dv else b(t_to)
+    return G.reshape((-1,) + comp)
+
+
+def upsampled_surface(X, n, psi_up, factor=4):
+    """(X_u, w_u) on the fine grid from the coarse nodes X: X_u = I_u X, w_u = psi_u W_u h_u^2."""
+    tc, tf = _grids(n, factor)
+    Xu = spline_resample(X, n, tc, tf)
+    xu = spline_resample(X, n, tc, tf, du=1)
+    xv = spline_resample(X, n, tc, tf, dv=1)
+    W = np.linalg.norm(np.cross(xu, xv), axis=1)
+    hf = np.pi / (factor * n + 1)
+    return Xu, np.asarray(psi_up, dtype=np.float64) * W * hf * hf
+
+
+def single_layer_upsampled(X, f, n, psi_up, mu=1.0, C=1.0, factor=4, nthreads=0):
+    """u at the coarse nodes: I_d S^{delta_u}[I_u f] evaluated on the upsampled surface."""
+    tc, tf = _grids(n, factor)
+    Xu, wu = upsampled_surface(X, n, psi_up, factor)
+    fu = spline_resample(f, n, tc, tf)
+    du = patch_delta(Xu, factor * n, C=C)
+    uu = single_layer(Xu, wu, fu, 0.0, mu=mu, delta_tgt=du, nthreads=nthreads)
+    return spline_resample(uu, factor * n, tf, tc)
+
+
 def smoothing(p: float):
     """(s1(p), s2(p)) as printed in Sec. 3.4."""
     lib = _load()

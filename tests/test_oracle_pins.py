@@ -304,3 +304,68 @@ def test_patch_delta_rejects_bad_arguments():
         oracle.patch_delta(np.zeros((10, 3)), 3)          # not whole patches
     with pytest.raises(ValueError):
         oracle.patch_delta(np.zeros((9, 3)), 3, C=0.0)
+
+
+# ---------------------------------------------------------------------------------------------
+# Upsampling sandwich (Sec. 3.4, "Upsampling"): I_u, W_u, w_u, I_d
+# ---------------------------------------------------------------------------------------------
+def test_spline_resample_reproduces_bicubics():
+    """Not-a-knot cubic splines reproduce every polynomial of degree <= 3 in each variable, and
+    its u- and v-derivatives; an asymmetric one catches swapped axes or patch order."""
+    import oracle
+    from capsule_inputs import fine_grid
+    n = 7
+    tc, tf = fine_grid(n)
+    P = lambda u, v, k: (1 + k) * (0.3 + u - 0.7 * u ** 3) * (2.0 - 0.4 * v ** 2 + 0.1 * v ** 3) + k * u * v
+    Pu = lambda u, v, k: (1 + k) * (1 - 2.1 * u ** 2) * (2.0 - 0.4 * v ** 2 + 0.1 * v ** 3) + k * v
+    Pv = lambda u, v, k: (1 + k) * (0.3 + u - 0.7 * u ** 3) * (-0.8 * v + 0.3 * v ** 2) + k * u
+    Uc, Vc = np.meshgrid(tc, tc, indexing="ij")
+    Uf, Vf = np.meshgrid(tf, tf, indexing="ij")
+    F = np.concatenate([P(Uc, Vc, k).ravel() for k in range(6)])
+    for du, dv, ref in ((0, 0, P), (1, 0, Pu), (0, 1, Pv)):
+        G = oracle.spline_resample(F, n, tc, tf, du=du, dv=dv)
+        want = np.concatenate([ref(Uf, Vf, k).ravel() for k in range(6)])
+        assert np.allclose(G, want, rtol=0, atol=1e-11)
+
+
+def test_upsampled_surface_converges_at_fourth_order():
+    """I_u X against the exact positions of the fine nodes: O(h^4) (ratio ~16 per halving of h);
+    the fine weights integrate the sphere's area 4 pi."""
+    import oracle
+    from capsule_inputs import fine_pou, fine_positions
+    errs, areas = [], []
+    for n in (8, 16, 32):
+        s = make_surface(SPHERE, n)
+        Xu, wu = oracle.upsampled_surface(s.X, n, fine_pou(n))
+        errs.append(np.abs(Xu - fine_positions(SPHERE, n)).max())
+        areas.append(abs(wu.sum() - 4 * math.pi))
+    assert errs[0] / errs[1] > 10 and errs[1] / errs[2] > 12, errs
+    assert areas[2] < 1e-4 and areas[2] < areas[0], areas
+
+
+def test_downsample_of_upsample_converges_to_identity():
+    """I_d I_u f -> f for a smooth density, at about fourth order."""
+    import oracle
+    from capsule_inputs import fine_grid
+    errs = []
+    for n in (8, 16, 32):
+        s = make_surface(RBC, n)
+        f = sh_force(s.x0, 4)
+        tc, tf = fine_grid(n)
+        back = oracle.spline_resample(oracle.spline_resample(f, n, tc, tf), 4 * n, tf, tc)
+        errs.append(np.abs(back - f).max() / np.abs(f).max())
+    assert errs[0] / errs[1] > 6 and errs[1] / errs[2] > 10 and errs[2] < 1e-5, errs
+
+
+def test_upsampled_single_layer_on_the_sphere():
+    """The whole sandwich on the unit sphere under uniform traction gives 2a f / (3 mu) at the
+    nodes, converging under refinement."""
+    import oracle
+    from capsule_inputs import fine_pou
+    errs = []
+    for n in (6, 12):
+        s = make_surface(SPHERE, n)
+        f = np.tile([0.0, 0.0, 1.0], (s.N, 1))
+        u = oracle.single_layer_upsampled(s.X, f, n, fine_pou(n), mu=1.0)
+        errs.append(np.abs(u - [0.0, 0.0, 2.0 / 3.0]).max())
+    assert errs[1] < 2e-5 and errs[1] < errs[0], errs

@@ -11,7 +11,8 @@ from . import _binding
 from ._binding import (EXPORTED, SL_EBUSY, SL_EHIP, SL_EINVAL, SL_ENOMEM, SL_ENOTFOUND, SL_ETIMEDOUT,
                        SL_FP64, SL_MIXED, SL_OK, SL_PARAM_KERNEL_TIMING, SL_PARAM_RHO64,
                        SL_PARAM_TARGETS_PER_LANE, SL_PARAM_WAVES_PER_SIMD, SlError, check, load, sl_create,
-                       sl_destroy, sl_eval, sl_get_param, sl_get_stats, sl_last_error, sl_patch_delta, sl_poll,
+                       sl_destroy, sl_eval, sl_eval_upsampled, sl_get_param, sl_get_stats, sl_last_error,
+                       sl_patch_delta, sl_poll,
                        sl_request_bytes, sl_set_param, sl_submit, sl_surface_register,
                        sl_surface_release, sl_wait)
 
@@ -98,6 +99,24 @@ class Context:
                              Xs[2].data_ptr(), float(C), D.data_ptr(), _stream_handle(stream)),
               "sl_patch_delta")
         return D
+
+    def single_layer_upsampled(self, X, f, n, psi_up, mu=1.0, C=1.0, factor=4, precision="fp64",
+                               stream=None, out=None):
+        """u (N, 3) at the nodes X (n_patches n^2, 3) through the upsampling step: I_d S[I_u f]
+        on I_u X with fine POU values psi_up (n_patches (factor n)^2,) and delta_u = C delta*."""
+        import torch
+        Xs, fs = _soa(X), _soa(f)
+        npts = Xs.shape[1]
+        if n < 1 or npts % (n * n) != 0:
+            raise ValueError("X must hold whole patches of n x n nodes")
+        ps = psi_up.to(torch.float64).contiguous()
+        U = out if out is not None else torch.empty((3, npts), dtype=torch.float64, device=Xs.device)
+        check(sl_eval_upsampled(self.ptr, PRECISIONS[precision], npts // (n * n), int(n), int(factor),
+                                Xs[0].data_ptr(), Xs[1].data_ptr(), Xs[2].data_ptr(), ps.data_ptr(),
+                                fs[0].data_ptr(), fs[1].data_ptr(), fs[2].data_ptr(), float(C),
+                                float(mu), U[0].data_ptr(), U[1].data_ptr(), U[2].data_ptr(),
+                                _stream_handle(stream)), "sl_eval_upsampled")
+        return U.t()
 
     # -- serving ---------------------------------------------------------------------------
     def register_surface(self, X, w, delta) -> int:

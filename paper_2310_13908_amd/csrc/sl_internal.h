@@ -198,4 +198,6 @@ struct sl_ctx {
     std::vector<hipEvent_t> spare_events;
     uint64_t pair_launches = 0;
     double pair_ms = 0.0;
+    // spline matrices of the upsampling step, per (n, factor): device memory, freed by sl_destroy
+    std::unordered_map<int64_t, double *> splines;
 };

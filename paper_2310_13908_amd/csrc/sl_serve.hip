@@ -932,6 +932,10 @@ void sl_destroy(sl_ctx *ctx)
     for (auto &ev : ctx->timed)
         for (hipEvent_t e : {ev.e0, ev.e1}) (void)hipEventDestroy(e);
     for (auto ev : ctx->spare_events) (void)hipEventDestroy(ev);
+    if (!ctx->splines.empty()) {
+        (void)hipSetDevice(ctx->device);
+        for (auto &kv : ctx->splines) (void)hipFree(kv.second);
+    }
     delete ctx;
 }
 

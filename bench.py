@@ -134,6 +134,51 @@ def patch_delta_leg(P, ctx, prob, tens, log, steps=20, warmup=3):
     return res
 
 
+def upsample_leg(P, ctx, dev, log, steps=3, warmup=1):
+    """The paper's production form of the sum (Sec. 3.4, "Upsampling"): u = I_d S[I_u f] with a
+    4x spline upsampling per patch, delta* on the fine grid, on the C2 surface (N = 24,576 coarse
+    nodes, N_up = 393,216 fine nodes, 1.55e11 fine pairs); a step is sl_eval_upsampled.  The
+    oracle's sandwich is checked on the 6 x 24 x 24 surface (every node)."""
+    import numpy as np
+    import torch
+    import oracle
+    from capsule_inputs import RBC, fine_pou, make_surface, sh_force
+    from capsule_inputs import workloads as W
+    p = W.c2()
+    n = p.surface.n
+    X, _, F = resident(dev, p.surface.X, p.surface.w, p.f)
+    psi = torch.as_tensor(fine_pou(n), device=dev)
+    fine_pairs = float((16 * p.N) ** 2)
+    res = {"workload": "rbc_6x64x64_sh8 upsampled 4x (N_up = 393,216), delta_u = delta* (C = 1)",
+           "fine_pairs": fine_pairs}
+    outs = {}
+    for prec in ("fp64", "mixed"):
+        U = torch.empty((3, p.N), dtype=torch.float64, device=dev)
+        t = time_steps(lambda: ctx.single_layer_upsampled(X, F, n, psi, precision=prec, out=U), steps, warmup)
+        outs[prec] = U.t().cpu().numpy()
+        res[prec] = {"ms_per_step": round(t * 1e3, 3), "gpair_s": round(fine_pairs / t / 1e9, 1)}
+        log(f"[bench] upsampled C2 {prec}: {t * 1e3:.2f} ms/step  {res[prec]['gpair_s']:.0f} Gpair/s "
+            f"(fine pairs)")
+    res["mixed_vs_fp64"] = rel_inf(outs["mixed"], outs["fp64"])
+    # parity with the oracle at a size it finishes in seconds
+    m = 24
+    s = make_surface(RBC, m)
+    f = sh_force(s.x0, 64)
+    t0 = time.perf_counter()
+    ref = oracle.single_layer_upsampled(s.X, f, m, fine_pou(m))
+    tm = time.perf_counter() - t0
+    Xs, _, Fs = resident(dev, s.X, s.w, f)
+    ps = torch.as_tensor(fine_pou(m), device=dev)
+    res["oracle_check"] = {"surface": "rbc_6x24x24 (N_up = 55,296)", "oracle_s": round(tm, 2)}
+    for prec in ("fp64", "mixed"):
+        u = ctx.single_layer_upsampled(Xs, Fs, m, ps, precision=prec)
+        torch.cuda.synchronize()
+        res["oracle_check"][f"eps_{prec}"] = rel_inf(u.cpu().numpy(), ref)
+    log(f"[bench] upsampled: mixed vs fp64 {res['mixed_vs_fp64']:.2e}; vs oracle (6x24x24) fp64 "
+        f"{res['oracle_check']['eps_fp64']:.2e}, mixed {res['oracle_check']['eps_mixed']:.2e}")
+    return res
+
+
 def roofline(precision, pairs, near, kern_ms):
     flops = FLOPS_FAR * (pairs - near) + FLOPS_NEAR * near
     achieved = flops / (kern_ms * 1e-3) / 1e12
@@ -463,6 +508,7 @@ def main():
     if not args.no_extras:
         import oracle
         line["patch_delta"] = patch_delta_leg(P, ctx, prob, tens, log)
+        line["upsampled"] = upsample_leg(P, ctx, dev, log)
         p3 = W.c3()
         t3 = resident(dev, p3.surface.X, p3.surface.w, p3.f)
         big = {"workload": "rbc_6x256x256_sh8", "N": p3.N}

@@ -153,38 +153,95 @@ __global__ __launch_bounds__(256) void k_morton(const double *__restrict__ x,
 // Block b owns elements [b * kSortChunk, (b + 1) * kSortChunk) in every pass.  The counts of
 // pass p live in their own buffer, counted by the kernel that writes pass p's input.
 // ----------------------------------------------------------------------------------------
-// Exclusive scan, in place, of `total` counters laid out digit-major (one block); also clears
-// the counters of the following pass.
-__global__ __launch_bounds__(1024) void k_rs_scan(uint32_t *__restrict__ counts, int64_t total,
-                                                  uint32_t *__restrict__ next)
+// Exclusive scan of the (digit, block) counts of a pass for many blocks, in three launches:
+// per-segment sums (k_scan_sums, which also clears the next pass's counts), their exclusive
+// scan in one workgroup (k_scan_top), and the segment scans plus their offsets (k_scan_apply).
+// Integer sums: the result does not depend on the order.
+constexpr int kScanThreads = 1024;
+constexpr int kScanSeg = 4 * kScanThreads;   // counters per segment (four per thread)
+
+// Exclusive scan of one value per thread across the workgroup; returns the workgroup total.
+__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t &excl, uint32_t *sh)
 {
-    __shared__ uint32_t buf[2][1024];
-    const int t = threadIdx.x;
-    for (int64_t i = t; i < total; i += 1024) next[i] = 0u;
-    const int64_t per = (total + 1023) / 1024;
-    const int64_t b = t * per, e = b + per < total ? b + per : total;
-    uint32_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += counts[i];
-    buf[0][t] = s;
-    __syncthreads();
-    int src = 0;
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = buf[src][t] + (t >= off ? buf[src][t - off] : 0u);
-        buf[src ^ 1][t] = v;
-        src ^= 1;
-        __syncthreads();
+    const int t = threadIdx.x, lane = t % kWave, w = t / kWave;
+    uint32_t incl = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t u = __shfl_up(incl, o, kWave);
+        incl += lane >= o ? u : 0u;
     }
-    uint32_t run = buf[src][t] - s;   // exclusive prefix of this thread's segment
-    for (int64_t i = b; i < e; ++i) {
-        const uint32_t c = counts[i];
-        counts[i] = run;
+    if (lane == kWave - 1) sh[w] = incl;
+    __syncthreads();
+    uint32_t base = 0, total = 0;
+    for (int j = 0; j < (int)(blockDim.x / kWave); ++j) {
+        base += j < w ? sh[j] : 0u;
+        total += sh[j];
+    }
+    __syncthreads();
+    excl = base + incl - v;
+    return total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(const uint32_t *__restrict__ c, int64_t total,
+                                                            uint32_t *__restrict__ part,
+                                                            uint32_t *__restrict__ next)
+{
+    __shared__ uint32_t sh[kScanThreads / kWave];
+    for (int64_t i = (int64_t)blockIdx.x * kScanThreads + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * kScanThreads)
+        next[i] = 0u;
+    const int64_t base = (int64_t)blockIdx.x * kScanSeg;
+    uint32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t i = base + k * kScanThreads + threadIdx.x;
+        v += i < total ? c[i] : 0u;
+    }
+    uint32_t excl;
+    const uint32_t tot = block_exclusive_scan(v, excl, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(uint32_t *__restrict__ part, int n)
+{
+    __shared__ uint32_t sh[kScanThreads / kWave];
+    const int per = (n + kScanThreads - 1) / kScanThreads;
+    const int b = threadIdx.x * per, e = b + per < n ? b + per : n;
+    uint32_t v = 0;
+    for (int i = b; i < e; ++i) v += part[i];
+    uint32_t run;
+    block_exclusive_scan(v, run, sh);
+    for (int i = b; i < e; ++i) {
+        const uint32_t c = part[i];
+        part[i] = run;
         run += c;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(uint32_t *__restrict__ c, int64_t total,
+                                                             const uint32_t *__restrict__ part)
+{
+    __shared__ uint32_t sh[kScanThreads / kWave];
+    const int64_t i0 = (int64_t)blockIdx.x * kScanSeg + 4 * (int64_t)threadIdx.x;
+    uint32_t x[4], v = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        x[k] = i0 + k < total ? c[i0 + k] : 0u;
+        v += x[k];
+    }
+    uint32_t run;
+    block_exclusive_scan(v, run, sh);
+    run += part[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (i0 + k < total) c[i0 + k] = run;
+        run += x[k];
     }
 }
 
 // Scatter by the digit at `shift`; when `next` is set, also counts the digit at shift + 8 of
 // every element for the block that owns its new position.  `offs` holds the pass's counts,
-// exclusively scanned by k_rs_scan when `scanned`; otherwise (few blocks) every block takes its
+// exclusively scanned by k_scan_* when `scanned`; otherwise (few blocks) every block takes its
 // offsets from the raw counts itself: for digit d, the counts of all digits below d plus those
 // of digit d in the blocks before it.
 __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(
@@ -432,8 +489,8 @@ hipError_t launch_bbox(const double *ax, const double *ay, const double *az, int
 
 // k_morton counts pass 0's digits into counts[0] (cleared by k_bbox_partial) and clears
 // counts[1] and counts[2]; the scatter of pass p counts into counts[p + 1], and the last one
-// clears counts[0] for a following sort.  With more than kSortBlocksNoScan blocks, k_rs_scan
-// scans counts[p] before pass p (and clears counts[(p + 1) % 3] as well).
+// clears counts[0] for a following sort.  With more than kSortBlocksNoScan blocks, the three
+// k_scan_* kernels scan counts[p] before pass p (and clear counts[(p + 1) % 3] as well).
 hipError_t launch_sort_points(const double *x, const double *y, const double *z, int64_t n,
                               const PackScratch &ps, const uint32_t **order, hipStream_t st)
 {
@@ -447,9 +504,17 @@ hipError_t launch_sort_points(const double *x, const double *y, const double *z,
     const bool scan = nb > kSortBlocksNoScan;
     int cur = 0;
     for (int p = 0; p < kPasses; ++p) {
-        if (scan)
-            hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, ps.counts[p], (int64_t)256 * nb,
+        if (scan) {
+            // counts[(p + 2) % 3] (the previous pass's, consumed; pass 2's before pass 0, which
+            // k_scan_sums of pass 1 clears again) holds the segment sums
+            const int64_t total = (int64_t)256 * nb;
+            const int nseg = (int)((total + kScanSeg - 1) / kScanSeg);
+            uint32_t *part = ps.counts[(p + 2) % 3];
+            hipLaunchKernelGGL(k_scan_sums, dim3(nseg), dim3(kScanThreads), 0, st, ps.counts[p], total, part,
                                ps.counts[(p + 1) % 3]);
+            hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, st, part, nseg);
+            hipLaunchKernelGGL(k_scan_apply, dim3(nseg), dim3(kScanThreads), 0, st, ps.counts[p], total, part);
+        }
         hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kSortThreads), 0, st, ps.keys[cur],
                            ps.vals[cur], ps.keys[cur ^ 1], ps.vals[cur ^ 1], n, p * kDigitBits,
                            ps.counts[p], scan ? 1 : 0, nb, p + 1 < kPasses ? ps.counts[p + 1] : nullptr,

@@ -46,11 +46,11 @@ typedef enum {
 typedef enum {
     SL_FP64 = 0,        /* every pair in double precision; ~1e-15 relative to the exact sum */
     SL_MIXED = 1        /* pairs with rho = r/delta >= rho64 in single precision (smoothed for
-                           rho < 5, plain Stokeslet beyond, where s1 = s2 = 1 to single
-                           precision), summed per cluster of 64 sources and folded into a
-                           per-target two-sum (hi, lo) pair; pairs with rho < rho64 (default 1:
-                           the self term and the nearest neighbours, where s2 cancels) and the
-                           final per-target sum in double precision; ~1e-7 relative */
+                           rho < 5 from a table of cubics in rho^2, plain Stokeslet beyond, where
+                           s1 = s2 = 1 to single precision), summed per cluster of 64 sources and
+                           folded into a per-target two-sum (hi, lo) pair; pairs with rho < rho64
+                           (default 0: none) and the final per-target sum in double precision;
+                           ~1e-7 relative */
 } sl_precision;
 
 typedef struct sl_ctx sl_ctx;   /* opaque; one per device */
@@ -71,7 +71,7 @@ const char *sl_last_error(void);
 
 /* Tunables.
  * SL_PARAM_RHO64: in SL_MIXED, pairs with r/delta below this value are summed in double
- *   precision (finite, >= 0.5; default 1).  Serving requests take the value current at
+ *   precision (finite, >= 0; default 0: no such pairs).  Serving requests take the value current at
  *   sl_submit.
  * SL_PARAM_KERNEL_TIMING: 1 = bracket every pair-kernel launch of sl_eval with HIP events on
  *   the caller's stream and accumulate the elapsed time into sl_stats; 0 (default) = off.

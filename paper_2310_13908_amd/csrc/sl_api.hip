@@ -138,7 +138,7 @@ sl_status sl_set_param(sl_ctx *ctx, sl_param key, double value)
     if (!ctx) return fail(SL_EINVAL, "sl_set_param: ctx is NULL");
     if (key == SL_PARAM_RHO64) {
         if (!isfinite(value) || value < kRho64Min)
-            return fail(SL_EINVAL, "sl_set_param: rho64 must be finite and >= 0.5");
+            return fail(SL_EINVAL, "sl_set_param: rho64 must be finite and >= 0");
         std::lock_guard<std::mutex> l(ctx->mu);
         ctx->rho64 = value;
         return SL_OK;

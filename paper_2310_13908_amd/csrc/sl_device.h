@@ -25,8 +25,8 @@ constexpr int kPad = 256;            // point arrays are padded to a multiple of
 constexpr double kC0 = 0.376126389031837524632052967707181724;   // 2 / (3 sqrt(pi))
 constexpr double kRhoExact64 = 6.9;  // s1 = s2 = 1 in double precision beyond this r/delta
 constexpr double kRhoExact32 = 5.0;  // ... and in single precision beyond this r/delta
-constexpr double kRho64Min = 0.5;    // smallest double-precision zone of the mixed path (the
-                                     // single-precision smoothing is fitted on 0.5 <= p < 5)
+constexpr double kRho64Min = 0.0;    // smallest double-precision zone of the mixed path: none
+                                     // (the single-precision smoothing table spans 0 <= p < 5)
 
 // 1/sqrt(x) for finite x > 0 to ~1 ulp: hardware estimate (good to about 2^-23 relative)
 // refined by one third-order step y (1 + e/2 + 3e^2/8), e = 1 - x y^2.

@@ -187,7 +187,7 @@ struct sl_ctx {
     int device = 0;
     int n_cu = 0;
     size_t budget = 0;
-    double rho64 = 1.0;
+    double rho64 = 0.0;
     int targets_per_lane = 0;   // 0: chosen per call
     int waves_per_simd = 32;
     std::mutex mu;

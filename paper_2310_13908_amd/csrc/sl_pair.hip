@@ -173,7 +173,7 @@ __device__ __forceinline__ void far_cluster(const Src &S, int64_t j0, Acc<R, VAR
 // state lives in LDS (`zs`: per target of the lane, x, y, z and the three sums, 64 apart): it is
 // needed only for the few sources with such a pair, and keeping it out of the vector registers
 // buys the kernel two more waves per SIMD.
-template <int R, bool VARD, bool MIXED>
+template <int R, bool VARD, bool MIXED, bool ZONE>
 __device__ __forceinline__ void near_cluster(const Src &S, int64_t j0, const DeltaC &dcu,
                                              const DeltaC32 &dcu32, const float4 *tab, double *zs,
                                              Acc<R, VARD, MIXED> &A)
@@ -192,11 +192,14 @@ __device__ __forceinline__ void near_cluster(const Src &S, int64_t j0, const Del
                 const DeltaC32 &d32 = VARD ? A.dc32[VARD ? r : 0] : dcu32;
                 near_pair32(A.tx32[r], A.ty32[r], A.tz32[r], sx32, sy32, sz32, gx32, gy32, gz32, d32,
                             tab, px[r], py[r], pz[r]);
-                float dx, dy, dz;
-                z64[r] = diff32(A.tx32[r], A.ty32[r], A.tz32[r], sx32, sy32, sz32, dx, dy, dz) < d32.cut2_64;
-                any = any || z64[r];
+                if constexpr (ZONE) {
+                    float dx, dy, dz;
+                    z64[r] = diff32(A.tx32[r], A.ty32[r], A.tz32[r], sx32, sy32, sz32, dx, dy, dz) <
+                             d32.cut2_64;
+                    any = any || z64[r];
+                }
             }
-            if (__builtin_amdgcn_ballot_w64(any)) {
+            if (ZONE && __builtin_amdgcn_ballot_w64(any)) {
                 const double *e = S.d + (j0 + j) * 8;
                 const double sx = e[0], sy = e[1], sz = e[2], gx = e[3], gy = e[4], gz = e[5];
                 const int lane = threadIdx.x % kWave;
@@ -243,7 +246,7 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
 // ballots, and this way's clusters are processed in ascending cluster order.  Every wave of a
 // group walks the same clusters, so the group's waves share each source record in the scalar
 // cache.
-template <int R, bool VARD, bool MIXED>
+template <int R, bool VARD, bool MIXED, bool ZONE>
 __device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec &rec,
                                           const TBlockRec &own, bool grouped, const Src &S,
                                           const double4 *__restrict__ sphere, const float4 *tab,
@@ -269,11 +272,13 @@ __device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec &re
             A.tx32[r] = a.t.x32[i];
             A.ty32[r] = a.t.y32[i];
             A.tz32[r] = a.t.z32[i];
-            double *z = zs + r * 6 * kWave + lane;
-            z[0] = A.tx[r];
-            z[kWave] = A.ty[r];
-            z[2 * kWave] = A.tz[r];
-            z[3 * kWave] = z[4 * kWave] = z[5 * kWave] = 0.0;
+            if constexpr (ZONE) {
+                double *z = zs + r * 6 * kWave + lane;
+                z[0] = A.tx[r];
+                z[kWave] = A.ty[r];
+                z[2 * kWave] = A.tz[r];
+                z[3 * kWave] = z[4 * kWave] = z[5 * kWave] = 0.0;
+            }
         }
         A.ax[r] = A.ay[r] = A.az[r] = 0.0;
         A.hx[r] = A.hy[r] = A.hz[r] = A.lx[r] = A.ly[r] = A.lz[r] = 0.0f;
@@ -303,7 +308,7 @@ __device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec &re
             if (((mf >> b) & 1) || (grouped && cluster_is_far(own, sphere[c0 + b])))
                 far_cluster<R, VARD, MIXED>(S, j0, A);
             else
-                near_cluster<R, VARD, MIXED>(S, j0, dcu, dcu32, tab, zs, A);
+                near_cluster<R, VARD, MIXED, ZONE>(S, j0, dcu, dcu32, tab, zs, A);
         }
     }
 
@@ -314,10 +319,16 @@ __device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec &re
     for (int r = 0; r < R; ++r) {
         const int64_t i = t0 + r * kWave + lane;
         if constexpr (MIXED) {
-            const double *z = zs + r * 6 * kWave + lane;
-            px[i] = z[3 * kWave] + ((double)A.hx[r] + (double)A.lx[r]);
-            py[i] = z[4 * kWave] + ((double)A.hy[r] + (double)A.ly[r]);
-            pz[i] = z[5 * kWave] + ((double)A.hz[r] + (double)A.lz[r]);
+            double zx = 0.0, zy = 0.0, zz = 0.0;
+            if constexpr (ZONE) {
+                const double *z = zs + r * 6 * kWave + lane;
+                zx = z[3 * kWave];
+                zy = z[4 * kWave];
+                zz = z[5 * kWave];
+            }
+            px[i] = zx + ((double)A.hx[r] + (double)A.lx[r]);
+            py[i] = zy + ((double)A.hy[r] + (double)A.ly[r]);
+            pz[i] = zz + ((double)A.hz[r] + (double)A.lz[r]);
         } else {
             px[i] = A.ax[r];
             py[i] = A.ay[r];
@@ -328,8 +339,9 @@ __device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec &re
 
 // Occupancy-sized grid of workgroups of G waves.  A workgroup pulls (group, way) items off the
 // counter; wave w of the workgroup takes target block G * group + w.  Items are group-major, so
-// the K ways of a group run at about the same time.
-template <int R, bool VARD, bool MIXED, int G>
+// the K ways of a group run at about the same time.  ZONE (mixed path only): some near pairs are
+// summed in double precision (rho64 > 0); without it the zone's code and LDS state are left out.
+template <int R, bool VARD, bool MIXED, bool ZONE, int G>
 __global__ __launch_bounds__(G * kWave) void k_pair(PairArgs a, const TBlockRec *__restrict__ recs,
                                                     const double *__restrict__ Sd,
                                                     const float *__restrict__ Sf,
@@ -342,7 +354,7 @@ __global__ __launch_bounds__(G * kWave) void k_pair(PairArgs a, const TBlockRec 
     __shared__ float4 sh_tab[MIXED ? kTab32Rows : 1];
     if constexpr (MIXED) load_tab32(sh_tab);
     // Mixed path: the double-precision zone's per-target state, R * 6 * 64 doubles per wave.
-    __shared__ double sh_zone[MIXED ? G * R * 6 * kWave : 1];
+    __shared__ double sh_zone[MIXED && ZONE ? G * R * 6 * kWave : 1];
     const Src S{Sd, Sf};
     const uint32_t K = (uint32_t)a.n_ways;
     const int n_groups = (a.n_tblocks + G - 1) / G;
@@ -357,9 +369,10 @@ __global__ __launch_bounds__(G * kWave) void k_pair(PairArgs a, const TBlockRec 
         const int g = (int)(item / K);
         const int tb = g * G + w;
         if (tb < a.n_tblocks)
-            pair_item<R, VARD, MIXED>(a, recs[g], recs[G > 1 ? n_groups + tb : g], G > 1, S, sphere,
-                                      sh_tab, sh_zone + (MIXED ? w * R * 6 * kWave : 0), part, tb,
-                                      (int)(item % K));
+            pair_item<R, VARD, MIXED, ZONE>(a, recs[g], recs[G > 1 ? n_groups + tb : g], G > 1, S,
+                                            sphere, sh_tab,
+                                            sh_zone + (MIXED && ZONE ? w * R * 6 * kWave : 0), part,
+                                            tb, (int)(item % K));
     }
 }
 
@@ -430,7 +443,7 @@ template <int R>
 hipError_t launch_r(const PairArgs &a, const PairPlan &p, bool mixed, bool vard, hipStream_t st,
                     const PairTiming *tm)
 {
-    static int occ[4] = {0, 0, 0, 0};
+    static int occ[6] = {0, 0, 0, 0, 0, 0};
     const int G = mixed ? group_size<true>() : group_size<false>();
     const int n_groups = (p.n_tblocks + G - 1) / G;
     TBlockRec *rec = reinterpret_cast<TBlockRec *>(a.tblock_scratch);
@@ -448,15 +461,20 @@ hipError_t launch_r(const PairArgs &a, const PairPlan &p, bool mixed, bool vard,
     }
     if (tm && tm->e0) (void)hipEventRecord(tm->e0, st);
     const int64_t n_items = (int64_t)n_groups * p.n_ways;
-#define SL_PAIR_LAUNCH(V, M, SLOT)                                                                  \
-    hipLaunchKernelGGL((k_pair<R, V, M, group_size<M>()>),                                           \
-                       dim3(work_grid(k_pair<R, V, M, group_size<M>()>, group_size<M>() * kWave, occ[SLOT], \
-                                      p.n_cu, n_items)),                                             \
+    const bool zone = mixed && a.rho64 > 0.0;
+#define SL_PAIR_LAUNCH(V, M, Z, SLOT)                                                               \
+    hipLaunchKernelGGL((k_pair<R, V, M, Z, group_size<M>()>),                                        \
+                       dim3(work_grid(k_pair<R, V, M, Z, group_size<M>()>, group_size<M>() * kWave,   \
+                                      occ[SLOT], p.n_cu, n_items)),                                  \
                        dim3(group_size<M>() * kWave), 0, st, a, rec, s.d, s.f32, s.sphere, a.part, ctr)
     if (vard) {
-        if (mixed) SL_PAIR_LAUNCH(true, true, 3); else SL_PAIR_LAUNCH(true, false, 1);
+        if (zone) SL_PAIR_LAUNCH(true, true, true, 3);
+        else if (mixed) SL_PAIR_LAUNCH(true, true, false, 5);
+        else SL_PAIR_LAUNCH(true, false, false, 1);
     } else {
-        if (mixed) SL_PAIR_LAUNCH(false, true, 2); else SL_PAIR_LAUNCH(false, false, 0);
+        if (zone) SL_PAIR_LAUNCH(false, true, true, 2);
+        else if (mixed) SL_PAIR_LAUNCH(false, true, false, 4);
+        else SL_PAIR_LAUNCH(false, false, false, 0);
     }
 #undef SL_PAIR_LAUNCH
     if (tm && tm->e1) (void)hipEventRecord(tm->e1, st);

@@ -240,6 +240,7 @@ __device__ void run_pair(const ServeArgs &a, const WorkItem &it, const float4 *t
     const double gap_far = mixed ? rec.gap_far_mixed : rec.gap_far;
     const DeltaC dc = make_delta(delta);
     const DeltaC32 dc32 = make_delta32(delta, dfield(&dd->rho64));
+    const bool zone = mixed && dc32.cut2_64 > 0.0f;   // some near pairs in double precision
     double tx[R], ty[R], tz[R], ax[R], ay[R], az[R];
     float tx32[R], ty32[R], tz32[R], hx[R], hy[R], hz[R], lx[R], ly[R], lz[R];
 #pragma unroll
@@ -262,7 +263,7 @@ __device__ void run_pair(const ServeArgs &a, const WorkItem &it, const float4 *t
             st.f[2 * lane] = make_float4(sx32[j0 + lane], sy32[j0 + lane], sz32[j0 + lane], gx32[j0 + lane]);
             st.f[2 * lane + 1] = make_float4(gy32[j0 + lane], gz32[j0 + lane], 0.0f, 0.0f);
         }
-        if (!mixed || !far) {
+        if (!mixed || (!far && zone)) {
             st.d[2 * lane] = make_double4(sx[j0 + lane], sy[j0 + lane], sz[j0 + lane], gx[j0 + lane]);
             st.d[2 * lane + 1] = make_double4(gy[j0 + lane], gz[j0 + lane], 0.0, 0.0);
         }
@@ -304,7 +305,8 @@ __device__ void run_pair(const ServeArgs &a, const WorkItem &it, const float4 *t
                     near_pair32(tx32[r], ty32[r], tz32[r], u.x, u.y, u.z, u.w, v.x, v.y, dc32, tab,
                                 px[r], py[r], pz[r]);
                     float ex, ey, ez;
-                    z64[r] = diff32(tx32[r], ty32[r], tz32[r], u.x, u.y, u.z, ex, ey, ez) < dc32.cut2_64;
+                    z64[r] = zone &&
+                             diff32(tx32[r], ty32[r], tz32[r], u.x, u.y, u.z, ex, ey, ez) < dc32.cut2_64;
                     any = any || z64[r];
                 }
                 if (__builtin_amdgcn_ballot_w64(any)) {
@@ -597,7 +599,7 @@ struct HostReq {
     const double *fx, *fy, *fz;
     double *ux, *uy, *uz;
     double mu = 1.0;
-    double rho64 = 1.0;
+    double rho64 = 0.0;
     ReqState state = ReqState::Pending;
     int slot = -1;
     char *staging = nullptr;

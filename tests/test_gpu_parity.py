@@ -147,11 +147,12 @@ def test_per_target_delta(ctx, precision):
     assert eps(u, ref) < TOL[precision]
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_smoothing_profile_single_source(ctx, precision):
+@pytest.mark.parametrize("precision,rho64", [("fp64", 0.0), ("mixed", 0.0), ("mixed", 1.0)])
+def test_smoothing_profile_single_source(ctx, precision, rho64):
     """One source, targets at r/delta from 0 (coincident) through the series/fit switch (0.5)
     and the exact-smoothing cut (6.9) to 9, in many directions: every target's velocity is a
-    single pair term, so this checks the device s1/r and s2/r^3 per target, not in a norm."""
+    single pair term, so this checks the device s1/r and s2/r^3 per target, not in a norm.
+    Mixed runs once without a double-precision zone (the default) and once with rho64 = 1."""
     import oracle
     rng = np.random.default_rng(17)
     delta = 0.037
@@ -162,15 +163,19 @@ def test_smoothing_profile_single_source(ctx, precision):
     src = np.array([[0.31, -0.72, 0.18]])
     T = src + rho[:, None] * delta * dirs
     g = np.array([[0.8, -1.3, 0.45]])
-    u = gpu_eval(ctx, src, [0.02], g, delta, targets=T, precision=precision)
+    ctx.set_rho64(rho64)
+    try:
+        u = gpu_eval(ctx, src, [0.02], g, delta, targets=T, precision=precision)
+    finally:
+        ctx.set_rho64(0.0)
     ref = oracle.single_layer(src, [0.02], g, delta, targets=T)
     rel = np.linalg.norm(u - ref, axis=1) / np.linalg.norm(ref, axis=1)
-    # FP64: double precision everywhere.  Mixed: double precision below r/delta = rho64 = 1,
-    # single precision (smoothed below 5) beyond -- a per-pair bound there, not the norm bound.
+    # FP64: double precision everywhere.  Mixed: double precision below r/delta = rho64, single
+    # precision (smoothed below 5) elsewhere -- a per-pair bound there, not the norm bound.
     if precision == "fp64":
         tol = np.full(rho.shape, 2e-14)
     else:
-        tol = np.where(rho < 0.99, 2e-14, 3e-6)
+        tol = np.where(rho < 0.99 * rho64, 2e-14, 3e-6)
     assert np.all(rel <= tol), (rho[rel > tol][:5], rel[rel > tol][:5])
 
 
@@ -264,21 +269,23 @@ def test_invalid_arguments(ctx):
 
 
 def test_rho64_parameter(ctx, c2_ref):
-    """A larger double-precision zone in the mixed path moves the result towards FP64."""
+    """A larger double-precision zone in the mixed path moves the result towards FP64; the
+    default is no zone."""
     p, ref = c2_ref
     import paper_2310_13908_amd as P
-    assert P.sl_set_param(ctx.ptr, P.SL_PARAM_RHO64, 0.4) == P.SL_EINVAL
-    assert P.sl_get_param(ctx.ptr, P.SL_PARAM_RHO64) == 1.0
+    assert P.sl_set_param(ctx.ptr, P.SL_PARAM_RHO64, -0.1) == P.SL_EINVAL
+    assert P.sl_set_param(ctx.ptr, P.SL_PARAM_RHO64, float("nan")) == P.SL_EINVAL
+    assert P.sl_get_param(ctx.ptr, P.SL_PARAM_RHO64) == 0.0
     errs = {}
     try:
-        for rho64 in (0.5, 1.0, 5.0, 12.0):
+        for rho64 in (0.0, 0.5, 1.0, 5.0, 12.0):
             ctx.set_rho64(rho64)
             errs[rho64] = eps(gpu_eval(ctx, p.surface.X, p.surface.w, p.f, p.delta,
                                        precision="mixed"), ref)
     finally:
-        ctx.set_rho64(1.0)
+        ctx.set_rho64(0.0)
     assert all(e < TOL["mixed"] for e in errs.values()), errs
-    assert errs[12.0] < errs[1.0]
+    assert errs[12.0] < errs[0.0] and errs[12.0] < errs[1.0]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])

@@ -46,8 +46,11 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_requests_match_oracle(ctx, surfaces, refs, precision):
+@pytest.mark.parametrize("precision,rho64", [("fp64", 0.0), ("mixed", 0.0), ("mixed", 1.0)])
+def test_requests_match_oracle(ctx, surfaces, refs, precision, rho64):
+    """Mixed runs without a double-precision zone (the default) and with rho64 = 1, which a
+    request takes from the context when it is submitted."""
+    ctx.set_rho64(rho64)
     hs = [ctx.register_surface(dev_t(s.X), dev_t(s.w), d) for s, f, d in surfaces]
     rids = [ctx.submit(h, dev_t(f), mu=0.8, precision=precision)[0]
             for h, (s, f, d) in zip(hs, surfaces)]

@@ -134,8 +134,24 @@ struct Acc {
     DeltaC32 dc32[VARD ? R : 1];
 };
 
-template <int R, bool VARD, bool MIXED>
-__device__ __forceinline__ void far_cluster(const Src &S, int64_t j0, Acc<R, VARD, MIXED> &A)
+// Source record j of the cluster at j0 in single precision: from the wave's LDS copy of the
+// cluster (STAGE) or, wave-uniform, from memory through scalar loads.
+template <bool STAGE>
+__device__ __forceinline__ void src32(const Src &S, int64_t j0, const float4 *stg, int j, float &sx,
+                                      float &sy, float &sz, float &gx, float &gy, float &gz)
+{
+    if constexpr (STAGE) {
+        const float4 u = stg[2 * j], v = stg[2 * j + 1];
+        sx = u.x; sy = u.y; sz = u.z; gx = u.w; gy = v.x; gz = v.y;
+    } else {
+        const float *q = S.f + (j0 + j) * 8;
+        sx = q[0]; sy = q[1]; sz = q[2]; gx = q[3]; gy = q[4]; gz = q[5];
+    }
+}
+
+template <int R, bool VARD, bool MIXED, bool STAGE>
+__device__ __forceinline__ void far_cluster(const Src &S, int64_t j0, const float4 *stg,
+                                            Acc<R, VARD, MIXED> &A)
 {
     if constexpr (MIXED) {
         float px[R], py[R], pz[R];
@@ -143,8 +159,8 @@ __device__ __forceinline__ void far_cluster(const Src &S, int64_t j0, Acc<R, VAR
         for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
 #pragma unroll 4
         for (int j = 0; j < kCluster; ++j) {
-            const float *q = S.f + (j0 + j) * 8;
-            const float sx = q[0], sy = q[1], sz = q[2], gx = q[3], gy = q[4], gz = q[5];
+            float sx, sy, sz, gx, gy, gz;
+            src32<STAGE>(S, j0, stg, j, sx, sy, sz, gx, gy, gz);
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 far_pair32(A.tx32[r], A.ty32[r], A.tz32[r], sx, sy, sz, gx, gy, gz, px[r], py[r], pz[r]);
@@ -173,10 +189,10 @@ __device__ __forceinline__ void far_cluster(const Src &S, int64_t j0, Acc<R, VAR
 // state lives in LDS (`zs`: per target of the lane, x, y, z and the three sums, 64 apart): it is
 // needed only for the few sources with such a pair, and keeping it out of the vector registers
 // buys the kernel two more waves per SIMD.
-template <int R, bool VARD, bool MIXED, bool ZONE>
-__device__ __forceinline__ void near_cluster(const Src &S, int64_t j0, const DeltaC &dcu,
-                                             const DeltaC32 &dcu32, const float4 *tab, double *zs,
-                                             Acc<R, VARD, MIXED> &A)
+template <int R, bool VARD, bool MIXED, bool ZONE, bool STAGE>
+__device__ __forceinline__ void near_cluster(const Src &S, int64_t j0, const float4 *stg,
+                                             const DeltaC &dcu, const DeltaC32 &dcu32,
+                                             const float4 *tab, double *zs, Acc<R, VARD, MIXED> &A)
 {
     if constexpr (MIXED) {
         float px[R], py[R], pz[R];
@@ -184,8 +200,8 @@ __device__ __forceinline__ void near_cluster(const Src &S, int64_t j0, const Del
         for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
 #pragma unroll 1
         for (int j = 0; j < kCluster; ++j) {
-            const float *q = S.f + (j0 + j) * 8;
-            const float sx32 = q[0], sy32 = q[1], sz32 = q[2], gx32 = q[3], gy32 = q[4], gz32 = q[5];
+            float sx32, sy32, sz32, gx32, gy32, gz32;
+            src32<STAGE>(S, j0, stg, j, sx32, sy32, sz32, gx32, gy32, gz32);
             bool z64[R], any = false;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -246,11 +262,12 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
 // ballots, and this way's clusters are processed in ascending cluster order.  Every wave of a
 // group walks the same clusters, so the group's waves share each source record in the scalar
 // cache.
-template <int R, bool VARD, bool MIXED, bool ZONE>
+template <int R, bool VARD, bool MIXED, bool ZONE, bool STAGE>
 __device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec &rec,
                                           const TBlockRec &own, bool grouped, const Src &S,
                                           const double4 *__restrict__ sphere, const float4 *tab,
-                                          double *zs, double *__restrict__ part, int tb, int k)
+                                          double *zs, float4 *stg, double *__restrict__ part, int tb,
+                                          int k)
 {
     const uint32_t K = (uint32_t)a.n_ways;
     const int lane = threadIdx.x % kWave;
@@ -304,11 +321,19 @@ __device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec &re
             const int b = __builtin_ctzll(m);
             m &= m - 1;
             const int64_t j0 = (c0 + b) * kCluster;
+            if constexpr (STAGE) {
+                // one record per lane; the wave reads back only what it wrote, after it, and a
+                // wave's LDS operations complete in order
+                const float4 *q = reinterpret_cast<const float4 *>(S.f + (j0 + lane) * 8);
+                const float4 u = q[0], v = q[1];
+                stg[2 * lane] = u;
+                stg[2 * lane + 1] = v;
+            }
             // near for the group, yet possibly far for this wave's own block
             if (((mf >> b) & 1) || (grouped && cluster_is_far(own, sphere[c0 + b])))
-                far_cluster<R, VARD, MIXED>(S, j0, A);
+                far_cluster<R, VARD, MIXED, STAGE>(S, j0, stg, A);
             else
-                near_cluster<R, VARD, MIXED, ZONE>(S, j0, dcu, dcu32, tab, zs, A);
+                near_cluster<R, VARD, MIXED, ZONE, STAGE>(S, j0, stg, dcu, dcu32, tab, zs, A);
         }
     }
 
@@ -355,6 +380,11 @@ __global__ __launch_bounds__(G * kWave) void k_pair(PairArgs a, const TBlockRec 
     if constexpr (MIXED) load_tab32(sh_tab);
     // Mixed path: the double-precision zone's per-target state, R * 6 * 64 doubles per wave.
     __shared__ double sh_zone[MIXED && ZONE ? G * R * 6 * kWave : 1];
+    // Mixed path without the zone: each wave's copy of the cluster it works on, so that the
+    // source loops take the source as a vector operand (an LDS broadcast) rather than a scalar
+    // one, which halves the issue rate of single-precision instructions.
+    constexpr bool STAGE = MIXED && !ZONE;
+    __shared__ float4 sh_stage[STAGE ? G * 2 * kCluster : 1];
     const Src S{Sd, Sf};
     const uint32_t K = (uint32_t)a.n_ways;
     const int n_groups = (a.n_tblocks + G - 1) / G;
@@ -369,10 +399,10 @@ __global__ __launch_bounds__(G * kWave) void k_pair(PairArgs a, const TBlockRec 
         const int g = (int)(item / K);
         const int tb = g * G + w;
         if (tb < a.n_tblocks)
-            pair_item<R, VARD, MIXED, ZONE>(a, recs[g], recs[G > 1 ? n_groups + tb : g], G > 1, S,
-                                            sphere, sh_tab,
-                                            sh_zone + (MIXED && ZONE ? w * R * 6 * kWave : 0), part,
-                                            tb, (int)(item % K));
+            pair_item<R, VARD, MIXED, ZONE, STAGE>(
+                a, recs[g], recs[G > 1 ? n_groups + tb : g], G > 1, S, sphere, sh_tab,
+                sh_zone + (MIXED && ZONE ? w * R * 6 * kWave : 0),
+                sh_stage + (STAGE ? w * 2 * kCluster : 0), part, tb, (int)(item % K));
     }
 }
 

@@ -7,7 +7,9 @@
 //      Morton-key kernel: deterministic),
 //   2. orders the points along a 24-bit Morton curve (stable LSD radix sort, three passes of
 //      8-bit digits; each pass's digit histogram is counted by the kernel that writes the
-//      pass's input, so a pass is two launches: scan and scatter),
+//      pass's input, so a pass is two launches: scan and scatter).  Up to 2^16 points the
+//      lowest digit is skipped: 2^16 cells of the curve's top 16 bits are already finer than
+//      the points, and points that share a cell keep their input order,
 //   3. gathers positions and the packed density g = w f (the trapezoid-POU weight of
 //      Sec. 3.3 folded into the force) into padded per-source records, plus the
 //      single-precision records used by the mixed path (positions relative to the box centre),
@@ -27,6 +29,7 @@ constexpr int kSortChunk = kSortThreads * kSortItems;   // elements per block an
 constexpr int kMortonBits = 8;                          // per axis
 constexpr int kDigitBits = 8;
 constexpr int kPasses = 3 * kMortonBits / kDigitBits;
+constexpr int64_t kTwoPassMaxN = 1 << 16;   // up to this many points, sort by the top 16 bits
 constexpr int kSortBlocksNoScan = 64;   // up to this many blocks, the scatters scan for themselves
 
 // ----------------------------------------------------------------------------------------
@@ -104,7 +107,7 @@ __global__ __launch_bounds__(256) void k_morton(const double *__restrict__ x,
                                                 uint32_t *__restrict__ keys,
                                                 uint32_t *__restrict__ vals,
                                                 uint32_t *__restrict__ counts, int nblocks,
-                                                uint32_t *__restrict__ clear1,
+                                                int shift0, uint32_t *__restrict__ clear1,
                                                 uint32_t *__restrict__ clear2, int64_t n_clear)
 {
     __shared__ double box[6];
@@ -144,7 +147,7 @@ __global__ __launch_bounds__(256) void k_morton(const double *__restrict__ x,
         const uint32_t k = morton3(qx, qy, qz);
         keys[i] = k;
         vals[i] = (uint32_t)i;
-        atomicAdd(&counts[(int64_t)(k & 255u) * nblocks + i / kSortChunk], 1u);
+        atomicAdd(&counts[(int64_t)((k >> shift0) & 255u) * nblocks + i / kSortChunk], 1u);
     }
 }
 
@@ -487,7 +490,7 @@ hipError_t launch_bbox(const double *ax, const double *ay, const double *az, int
     return hipGetLastError();
 }
 
-// k_morton counts pass 0's digits into counts[0] (cleared by k_bbox_partial) and clears
+// k_morton counts the first pass's digits into counts[0] (cleared by k_bbox_partial) and clears
 // counts[1] and counts[2]; the scatter of pass p counts into counts[p + 1], and the last one
 // clears counts[0] for a following sort.  With more than kSortBlocksNoScan blocks, the three
 // k_scan_* kernels scan counts[p] before pass p (and clear counts[(p + 1) % 3] as well).
@@ -496,14 +499,16 @@ hipError_t launch_sort_points(const double *x, const double *y, const double *z,
 {
     const int nb = sort_blocks(n);
     const int64_t mb = (n + 255) / 256;
+    const int passes = n <= kTwoPassMaxN ? kPasses - 1 : kPasses;
+    const int shift0 = (kPasses - passes) * kDigitBits;
     hipLaunchKernelGGL(k_morton, dim3((unsigned)(mb < 1024 ? mb : 1024)), dim3(256), 0, st, x, y, z, n,
                        ps.bbox_part, ps.n_bbox_parts, ps.bbox, ps.centre, ps.keys[0], ps.vals[0],
-                       ps.counts[0], nb, ps.counts[1], ps.counts[2], (int64_t)256 * nb);
+                       ps.counts[0], nb, shift0, ps.counts[1], ps.counts[2], (int64_t)256 * nb);
     // With few blocks every scatter block sums the raw counts itself (at most 64 per thread), and
     // the single-workgroup scan launches are skipped.
     const bool scan = nb > kSortBlocksNoScan;
     int cur = 0;
-    for (int p = 0; p < kPasses; ++p) {
+    for (int p = 0; p < passes; ++p) {
         if (scan) {
             // counts[(p + 2) % 3] (the previous pass's, consumed; pass 2's before pass 0, which
             // k_scan_sums of pass 1 clears again) holds the segment sums
@@ -516,9 +521,9 @@ hipError_t launch_sort_points(const double *x, const double *y, const double *z,
             hipLaunchKernelGGL(k_scan_apply, dim3(nseg), dim3(kScanThreads), 0, st, ps.counts[p], total, part);
         }
         hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kSortThreads), 0, st, ps.keys[cur],
-                           ps.vals[cur], ps.keys[cur ^ 1], ps.vals[cur ^ 1], n, p * kDigitBits,
-                           ps.counts[p], scan ? 1 : 0, nb, p + 1 < kPasses ? ps.counts[p + 1] : nullptr,
-                           p + 1 == kPasses ? ps.counts[0] : nullptr);
+                           ps.vals[cur], ps.keys[cur ^ 1], ps.vals[cur ^ 1], n, shift0 + p * kDigitBits,
+                           ps.counts[p], scan ? 1 : 0, nb, p + 1 < passes ? ps.counts[p + 1] : nullptr,
+                           p + 1 == passes ? ps.counts[0] : nullptr);
         cur ^= 1;
     }
     *order = ps.vals[cur];

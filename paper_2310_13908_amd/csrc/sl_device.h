@@ -326,8 +326,8 @@ __device__ __forceinline__ void smoothing32(float r2, const DeltaC32 &dc, const 
                                             float &K1, float &K2)
 {
     const float u = fminf(r2 * dc.tsc, (float)kTab32N - 0x1p-16f);
-    const int i = (int)u;
-    const float x = u - (float)i;
+    const int i = (int)u;                          // u >= 0: the floor
+    const float x = __builtin_amdgcn_fractf(u);    // u - floor(u), exact here
     const float4 a = tab[i];
     const float4 b = tab[kTab32N + i];
     K1 = fmaf(fmaf(fmaf(a.w, x, a.z), x, a.y), x, a.x) * dc.id;
@@ -347,12 +347,13 @@ __device__ __forceinline__ float diff32(float tx, float ty, float tz, float sx, 
 }
 
 // Near pair of the mixed path, single-precision zones: rho64 <= p < 5 smoothed, p >= 5 plain,
-// accumulated in (px, py, pz); p < rho64 (including r = 0) contributes nothing here -- the caller
-// sums that zone in double precision (zone_pair64), deciding it with the same diff32 test (the
-// self term and the nearest neighbours, where the difference of the positions cancels).  The
+// accumulated in (px, py, pz); with ZONE, p < rho64 (including r = 0) contributes nothing here --
+// the caller sums that zone in double precision (zone_pair64), deciding it with the same diff32
+// test.  Without it (rho64 = 0) every pair is summed here, r = 0 through the table's q = 0 row.  The
 // smoothing runs only when some lane of the wavefront needs it (a wave-uniform test), so a
 // source that is farther than 5 delta from all 64 targets of the wavefront costs what a far pair
 // costs.  `tab` is the single-precision smoothing table (load_tab32).
+template <bool ZONE = true>
 __device__ __forceinline__ void near_pair32(float tx32, float ty32, float tz32, float sx32,
                                             float sy32, float sz32, float gx32, float gy32,
                                             float gz32, const DeltaC32 &dc32, const float4 *tab,
@@ -360,7 +361,7 @@ __device__ __forceinline__ void near_pair32(float tx32, float ty32, float tz32, 
 {
     float dx, dy, dz;
     const float r2 = diff32(tx32, ty32, tz32, sx32, sy32, sz32, dx, dy, dz);
-    const bool z64 = r2 < dc32.cut2_64;
+    const bool z64 = ZONE && r2 < dc32.cut2_64;
     const bool z5 = r2 < dc32.cut2_5;
     const float ri = __builtin_amdgcn_rsqf(r2);
     float K1 = ri, K2 = ri * ri * ri;

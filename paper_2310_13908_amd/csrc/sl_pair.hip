@@ -198,7 +198,7 @@ __device__ __forceinline__ void near_cluster(const Src &S, int64_t j0, const flo
         float px[R], py[R], pz[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
-#pragma unroll 1
+#pragma unroll ZONE ? 1 : 2
         for (int j = 0; j < kCluster; ++j) {
             float sx32, sy32, sz32, gx32, gy32, gz32;
             src32<STAGE>(S, j0, stg, j, sx32, sy32, sz32, gx32, gy32, gz32);
@@ -206,8 +206,8 @@ __device__ __forceinline__ void near_cluster(const Src &S, int64_t j0, const flo
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const DeltaC32 &d32 = VARD ? A.dc32[VARD ? r : 0] : dcu32;
-                near_pair32(A.tx32[r], A.ty32[r], A.tz32[r], sx32, sy32, sz32, gx32, gy32, gz32, d32,
-                            tab, px[r], py[r], pz[r]);
+                near_pair32<ZONE>(A.tx32[r], A.ty32[r], A.tz32[r], sx32, sy32, sz32, gx32, gy32,
+                                  gz32, d32, tab, px[r], py[r], pz[r]);
                 if constexpr (ZONE) {
                     float dx, dy, dz;
                     z64[r] = diff32(A.tx32[r], A.ty32[r], A.tz32[r], sx32, sy32, sz32, dx, dy, dz) <

@@ -185,9 +185,158 @@ struct Stage {
     float4 *f;    // [kCluster][2]
 };
 
+// What a pair item reads of its request, and its target block's classification record.
+struct BlockView {
+    const double *sx, *sy, *sz, *gx, *gy, *gz;
+    const float *sx32, *sy32, *sz32, *gx32, *gy32, *gz32;
+    const int32_t *perm;
+    const double4 *sphere;
+    double *ux, *uy, *uz;
+    int64_t np;
+    double scale, gap_far;
+    TBlockRec rec;
+    DeltaC dc;
+    DeltaC32 dc32;
+};
+
+// The sums of the R * 64 targets from t0 on over every source cluster of the request, written
+// to the caller's arrays.  MIXED: single precision with the per-cluster two-sum, and with ZONE
+// the pairs below rho64 in double precision; otherwise every pair in double precision.
+template <bool MIXED, bool ZONE, int R>
+__device__ __forceinline__ void serve_targets(const BlockView &v, int64_t t0, const float4 *tab,
+                                              const Stage &st)
+{
+    constexpr bool F64 = !MIXED || ZONE;   // double-precision targets and sums
+    const int lane = threadIdx.x % kWave;
+    double tx[F64 ? R : 1], ty[F64 ? R : 1], tz[F64 ? R : 1];
+    double ax[F64 ? R : 1], ay[F64 ? R : 1], az[F64 ? R : 1];
+    float tx32[MIXED ? R : 1], ty32[MIXED ? R : 1], tz32[MIXED ? R : 1];
+    float hx[MIXED ? R : 1], hy[MIXED ? R : 1], hz[MIXED ? R : 1];
+    float lx[MIXED ? R : 1], ly[MIXED ? R : 1], lz[MIXED ? R : 1];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = t0 + r * kWave + lane;
+        if constexpr (F64) {
+            tx[r] = v.sx[i]; ty[r] = v.sy[i]; tz[r] = v.sz[i];
+            ax[r] = ay[r] = az[r] = 0.0;
+        }
+        if constexpr (MIXED) {
+            tx32[r] = v.sx32[i]; ty32[r] = v.sy32[i]; tz32[r] = v.sz32[i];
+            hx[r] = hy[r] = hz[r] = lx[r] = ly[r] = lz[r] = 0.0f;
+        }
+    }
+
+    const int64_t n_cl = v.np / kCluster;
+    for (int64_t c = 0; c < n_cl; ++c) {
+        const int64_t j0 = c * kCluster;
+        const bool far = uni64(cluster_is_far(v.rec, v.sphere[c], v.gap_far) ? 1u : 0u) != 0;
+        // stage what this cluster's loop reads
+        if constexpr (MIXED) {
+            st.f[2 * lane] = make_float4(v.sx32[j0 + lane], v.sy32[j0 + lane], v.sz32[j0 + lane],
+                                         v.gx32[j0 + lane]);
+            st.f[2 * lane + 1] = make_float4(v.gy32[j0 + lane], v.gz32[j0 + lane], 0.0f, 0.0f);
+        }
+        if (!MIXED || (ZONE && !far)) {
+            st.d[2 * lane] = make_double4(v.sx[j0 + lane], v.sy[j0 + lane], v.sz[j0 + lane],
+                                          v.gx[j0 + lane]);
+            st.d[2 * lane + 1] = make_double4(v.gy[j0 + lane], v.gz[j0 + lane], 0.0, 0.0);
+        }
+        if constexpr (MIXED) {
+            float px[R], py[R], pz[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
+            if (far) {
+#pragma unroll 4
+                for (int j = 0; j < kCluster; ++j) {
+                    const float4 u = st.f[2 * j], w = st.f[2 * j + 1];
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        far_pair32(tx32[r], ty32[r], tz32[r], u.x, u.y, u.z, u.w, w.x, w.y, px[r],
+                                   py[r], pz[r]);
+                }
+            } else {
+#pragma unroll 1
+                for (int j = 0; j < kCluster; ++j) {
+                    const float4 u = st.f[2 * j], w = st.f[2 * j + 1];
+                    bool z64[R], any = false;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        near_pair32<ZONE>(tx32[r], ty32[r], tz32[r], u.x, u.y, u.z, u.w, w.x, w.y,
+                                          v.dc32, tab, px[r], py[r], pz[r]);
+                        if constexpr (ZONE) {
+                            float ex, ey, ez;
+                            z64[r] = diff32(tx32[r], ty32[r], tz32[r], u.x, u.y, u.z, ex, ey, ez) <
+                                     v.dc32.cut2_64;
+                            any = any || z64[r];
+                        }
+                    }
+                    if constexpr (ZONE) {
+                        if (__builtin_amdgcn_ballot_w64(any)) {
+                            const double4 U = st.d[2 * j], V = st.d[2 * j + 1];
+#pragma unroll
+                            for (int r = 0; r < R; ++r)
+                                if (z64[r])
+                                    zone_pair64(tx[r], ty[r], tz[r], U.x, U.y, U.z, U.w, V.x, V.y,
+                                                v.dc, ax[r], ay[r], az[r]);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                two_sum_acc(px[r], hx[r], lx[r]);
+                two_sum_acc(py[r], hy[r], ly[r]);
+                two_sum_acc(pz[r], hz[r], lz[r]);
+            }
+        } else if (far) {
+#pragma unroll 2
+            for (int j = 0; j < kCluster; ++j) {
+                const double4 u = st.d[2 * j], w = st.d[2 * j + 1];
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    far_pair64(tx[r], ty[r], tz[r], u.x, u.y, u.z, u.w, w.x, w.y, ax[r], ay[r], az[r]);
+            }
+        } else {
+#pragma unroll 1
+            for (int j = 0; j < kCluster; ++j) {
+                const double4 u = st.d[2 * j], w = st.d[2 * j + 1];
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    near_pair64(tx[r], ty[r], tz[r], u.x, u.y, u.z, u.w, w.x, w.y, v.dc, ax[r], ay[r],
+                                az[r]);
+            }
+        }
+    }
+
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = t0 + r * kWave + lane;
+        const int32_t idx = v.perm[i];
+        if (idx >= 0) {
+            double ox, oy, oz;
+            if constexpr (MIXED) {
+                ox = (double)hx[r] + (double)lx[r];
+                oy = (double)hy[r] + (double)ly[r];
+                oz = (double)hz[r] + (double)lz[r];
+                if constexpr (ZONE) {
+                    ox = ax[r] + ox;
+                    oy = ay[r] + oy;
+                    oz = az[r] + oz;
+                }
+            } else {
+                ox = ax[r];
+                oy = ay[r];
+                oz = az[r];
+            }
+            v.ux[idx] = ox * v.scale;
+            v.uy[idx] = oy * v.scale;
+            v.uz[idx] = oz * v.scale;
+        }
+    }
+}
+
 __device__ void run_pair(const ServeArgs &a, const WorkItem &it, const float4 *tab, const Stage &st)
 {
-    constexpr int R = kServeR;
     const int lane = threadIdx.x % kWave;
     const ReqDesc *d = a.desc + it.slot;
     // Wait until the request's density is packed.  Its gather items were claimed before this
@@ -223,126 +372,32 @@ __device__ void run_pair(const ServeArgs &a, const WorkItem &it, const float4 *t
     }
 
     const ReqDesc *dd = a.ddesc + it.slot;   // written before the gathers finished
-    const double *sx = dfield(&dd->x), *sy = dfield(&dd->y), *sz = dfield(&dd->z);
-    const double *gx = dfield(&dd->gx), *gy = dfield(&dd->gy), *gz = dfield(&dd->gz);
-    const float *sx32 = dfield(&dd->x32), *sy32 = dfield(&dd->y32), *sz32 = dfield(&dd->z32);
-    const float *gx32 = dfield(&dd->gx32), *gy32 = dfield(&dd->gy32), *gz32 = dfield(&dd->gz32);
-    const int32_t *perm = dfield(&dd->perm);
-    const double4 *sphere = dfield(&dd->sphere);
+    BlockView v;
+    v.sx = dfield(&dd->x); v.sy = dfield(&dd->y); v.sz = dfield(&dd->z);
+    v.gx = dfield(&dd->gx); v.gy = dfield(&dd->gy); v.gz = dfield(&dd->gz);
+    v.sx32 = dfield(&dd->x32); v.sy32 = dfield(&dd->y32); v.sz32 = dfield(&dd->z32);
+    v.gx32 = dfield(&dd->gx32); v.gy32 = dfield(&dd->gy32); v.gz32 = dfield(&dd->gz32);
+    v.perm = dfield(&dd->perm);
+    v.sphere = dfield(&dd->sphere);
+    v.ux = dfield(&dd->ux); v.uy = dfield(&dd->uy); v.uz = dfield(&dd->uz);
+    v.np = dfield(&dd->np);
+    v.scale = dfield(&dd->scale);
+    const double delta = dfield(&dd->delta);
+    const bool mixed = dfield(&dd->mixed) != 0;
     const TBlockRec *tbr = dfield(&dd->tbr);
-    double *ux = dfield(&dd->ux), *uy = dfield(&dd->uy), *uz = dfield(&dd->uz);
-    const int64_t np = dfield(&dd->np);
-    const double delta = dfield(&dd->delta), scale = dfield(&dd->scale);
-    const int64_t mixed = dfield(&dd->mixed);
-
+    v.rec = tbr[it.a];
+    v.gap_far = mixed ? v.rec.gap_far_mixed : v.rec.gap_far;
+    v.dc = make_delta(delta);
+    v.dc32 = make_delta32(delta, dfield(&dd->rho64));
     const int64_t t0 = (int64_t)it.a * kServeBlock;
-    const TBlockRec rec = tbr[it.a];
-    const double gap_far = mixed ? rec.gap_far_mixed : rec.gap_far;
-    const DeltaC dc = make_delta(delta);
-    const DeltaC32 dc32 = make_delta32(delta, dfield(&dd->rho64));
-    const bool zone = mixed && dc32.cut2_64 > 0.0f;   // some near pairs in double precision
-    double tx[R], ty[R], tz[R], ax[R], ay[R], az[R];
-    float tx32[R], ty32[R], tz32[R], hx[R], hy[R], hz[R], lx[R], ly[R], lz[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t i = t0 + r * kWave + lane;
-        tx[r] = sx[i]; ty[r] = sy[i]; tz[r] = sz[i];
-        tx32[r] = mixed ? sx32[i] : 0.0f;
-        ty32[r] = mixed ? sy32[i] : 0.0f;
-        tz32[r] = mixed ? sz32[i] : 0.0f;
-        ax[r] = ay[r] = az[r] = 0.0;
-        hx[r] = hy[r] = hz[r] = lx[r] = ly[r] = lz[r] = 0.0f;
-    }
-
-    const int64_t n_cl = np / kCluster;
-    for (int64_t c = 0; c < n_cl; ++c) {
-        const int64_t j0 = c * kCluster;
-        const bool far = uni64(cluster_is_far(rec, sphere[c], gap_far) ? 1u : 0u) != 0;
-        // stage what this cluster's loop reads
-        if (mixed) {
-            st.f[2 * lane] = make_float4(sx32[j0 + lane], sy32[j0 + lane], sz32[j0 + lane], gx32[j0 + lane]);
-            st.f[2 * lane + 1] = make_float4(gy32[j0 + lane], gz32[j0 + lane], 0.0f, 0.0f);
-        }
-        if (!mixed || (!far && zone)) {
-            st.d[2 * lane] = make_double4(sx[j0 + lane], sy[j0 + lane], sz[j0 + lane], gx[j0 + lane]);
-            st.d[2 * lane + 1] = make_double4(gy[j0 + lane], gz[j0 + lane], 0.0, 0.0);
-        }
-        if (far && mixed) {
-            float px[R], py[R], pz[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
-#pragma unroll 4
-            for (int j = 0; j < kCluster; ++j) {
-                const float4 u = st.f[2 * j], v = st.f[2 * j + 1];
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                    far_pair32(tx32[r], ty32[r], tz32[r], u.x, u.y, u.z, u.w, v.x, v.y, px[r], py[r], pz[r]);
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                two_sum_acc(px[r], hx[r], lx[r]);
-                two_sum_acc(py[r], hy[r], ly[r]);
-                two_sum_acc(pz[r], hz[r], lz[r]);
-            }
-        } else if (far) {
-#pragma unroll 2
-            for (int j = 0; j < kCluster; ++j) {
-                const double4 u = st.d[2 * j], v = st.d[2 * j + 1];
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                    far_pair64(tx[r], ty[r], tz[r], u.x, u.y, u.z, u.w, v.x, v.y, ax[r], ay[r], az[r]);
-            }
-        } else if (mixed) {
-            float px[R], py[R], pz[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) px[r] = py[r] = pz[r] = 0.0f;
-#pragma unroll 1
-            for (int j = 0; j < kCluster; ++j) {
-                const float4 u = st.f[2 * j], v = st.f[2 * j + 1];
-                bool z64[R], any = false;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    near_pair32(tx32[r], ty32[r], tz32[r], u.x, u.y, u.z, u.w, v.x, v.y, dc32, tab,
-                                px[r], py[r], pz[r]);
-                    float ex, ey, ez;
-                    z64[r] = zone &&
-                             diff32(tx32[r], ty32[r], tz32[r], u.x, u.y, u.z, ex, ey, ez) < dc32.cut2_64;
-                    any = any || z64[r];
-                }
-                if (__builtin_amdgcn_ballot_w64(any)) {
-                    const double4 U = st.d[2 * j], V = st.d[2 * j + 1];
-#pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        if (z64[r]) zone_pair64(tx[r], ty[r], tz[r], U.x, U.y, U.z, U.w, V.x, V.y, dc,
-                                                ax[r], ay[r], az[r]);
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                two_sum_acc(px[r], hx[r], lx[r]);
-                two_sum_acc(py[r], hy[r], ly[r]);
-                two_sum_acc(pz[r], hz[r], lz[r]);
-            }
-        } else {
-#pragma unroll 1
-            for (int j = 0; j < kCluster; ++j) {
-                const double4 u = st.d[2 * j], v = st.d[2 * j + 1];
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                    near_pair64(tx[r], ty[r], tz[r], u.x, u.y, u.z, u.w, v.x, v.y, dc, ax[r], ay[r], az[r]);
-            }
-        }
-    }
-
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t i = t0 + r * kWave + lane;
-        const int32_t idx = perm[i];
-        if (idx >= 0) {
-            ux[idx] = (ax[r] + ((double)hx[r] + (double)lx[r])) * scale;
-            uy[idx] = (ay[r] + ((double)hy[r] + (double)ly[r])) * scale;
-            uz[idx] = (az[r] + ((double)hz[r] + (double)lz[r])) * scale;
-        }
+    // One instance per path, so that no path holds another's registers; the mixed path with the
+    // double-precision zone, whose pairs hold the most state, takes half of the targets at a time.
+    if (!mixed) {
+        serve_targets<false, false, kServeR>(v, t0, tab, st);
+    } else if (v.dc32.cut2_64 > 0.0f) {
+        for (int h = 0; h < kServeR; ++h) serve_targets<true, true, 1>(v, t0 + h * kWave, tab, st);
+    } else {
+        serve_targets<true, false, kServeR>(v, t0, tab, st);
     }
     __threadfence();
     if (lane == 0) {

@@ -95,9 +95,10 @@ def test_c3_rbc_sampled(ctx, precision):
 
 @pytest.mark.parametrize("n", [104, 105])
 def test_sort_paths_at_the_scan_threshold(ctx, n):
-    """N = 6 n^2 on either side of 64 sort blocks of 1024 keys (64,896 and 66,150 points): the
-    scatter passes take their offsets from the raw counts below it and from k_rs_scan above it.
-    Targets = sources and distinct targets (a second sort with the same scratch), 256 sampled
+    """N = 6 n^2 on either side of 2^16 = 64 sort blocks of 1024 keys (64,896 and 66,150 points):
+    below it two radix passes whose scatters take their offsets from the raw counts, above it
+    three passes with the three-kernel scan of the counts.  Targets = sources and distinct
+    targets (a second sort with the same scratch, two passes after three for n = 105), 256 sampled
     targets each against the oracle."""
     import oracle
     s = make_surface(RBC, n)
@@ -111,6 +112,22 @@ def test_sort_paths_at_the_scan_threshold(ctx, n):
         T = s.X[idx] * 1.001
         u = gpu_eval(ctx, s.X, s.w, f, d, targets=T, precision=precision)
         assert eps(u, oracle.single_layer(s.X, s.w, f, d, targets=T)) < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_sort_few_sources_many_targets(ctx, precision):
+    """4,704 sources (a two-pass sort) and 70,000 distinct targets (a three-pass sort with the
+    count scan) in one call: the second sort reuses the scratch of the first.  Every target
+    against the oracle."""
+    import oracle
+    s = make_surface(RBC, 28)
+    f = sh_force(s.x0, 41)
+    d = 2 * math.pi / 29
+    rng = np.random.default_rng(41)
+    T = s.X[rng.integers(0, s.N, 70000)] + rng.normal(scale=0.05, size=(70000, 3))
+    u = gpu_eval(ctx, s.X, s.w, f, d, targets=T, precision=precision)
+    ref = oracle.single_layer(s.X, s.w, f, d, targets=T)
+    assert eps(u, ref) < TOL[precision]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])

@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import math
 import os
@@ -26,17 +27,28 @@ FLOPS_FAR = 28                                   # plain Stokeslet pair
 FLOPS_NEAR = 49                                  # regularized pair (erf, exp, rsqrt = 1 each)
 RHO_EXACT64 = 6.9                                # s = 1 to double precision beyond this r/delta
 PMC_FILE = os.path.join(ROOT, "profiles", "pmc_pair_kernel.json")
-PAIR_SOURCES = ["paper_2310_13908_amd/csrc/sl_pair.hip", "paper_2310_13908_amd/csrc/sl_device.h"]
+PAIR_SOURCES = ["paper_2310_13908_amd/csrc/sl_pair.hip", "paper_2310_13908_amd/csrc/sl_device.h",
+                "paper_2310_13908_amd/csrc/sl_internal.h",
+                "paper_2310_13908_amd/csrc/sl_smoothing_coeffs.h"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def code_text(src: str) -> str:
+    """C++ source without comments and blank space: what the compiler sees of it."""
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
 def pair_kernel_sha() -> str:
+    """Hash of the pair kernel's code (comments and layout excluded): the PMC traffic stored
+    under profiles/ is reported only while it still matches."""
     h = hashlib.sha256()
     for p in PAIR_SOURCES:
-        h.update(open(os.path.join(ROOT, p), "rb").read())
+        h.update(code_text(open(os.path.join(ROOT, p)).read()).encode())
     return h.hexdigest()[:16]
 
 

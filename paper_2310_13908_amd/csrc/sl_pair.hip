@@ -3,15 +3,18 @@
 //
 // Work decomposition.  One wavefront owns a block of 64 R consecutive (spatially sorted)
 // targets, R per lane, held in registers.  Source data are wave-uniform: every lane needs the
-// same source at the same time, so the sources are read with scalar loads into scalar
-// registers -- no LDS staging, and every VALU instruction takes the source as a scalar operand.
-// The G waves of a workgroup (mixed path) own G adjacent target blocks and walk the same source
-// clusters, so a source record fetched into the scalar cache by one of them serves the others.
+// same source at the same time.  The mixed kernel without the double-precision zone copies each
+// cluster it walks into the wave's own LDS area and reads every record back as a broadcast, so
+// that its single-precision instructions take the source as a vector operand (a scalar operand
+// halves their issue rate); the other kernels read sources with scalar loads into scalar
+// registers.  The G waves of a workgroup (mixed path) own G adjacent target blocks and walk the
+// same source clusters, so a record fetched by one of them is in cache for the others.
 //
 // Each (target group, source cluster of 64) pair is classified once by the bounding spheres:
 //   far  (gap >= cut * delta_max): plain Stokeslet, 28 flops a pair, no erf/exp;
-//   near: regularized kernel (double precision, or the mixed path's three zones), with the
-//         smoothing evaluated only where some lane of the wavefront needs it.
+//   near: regularized kernel (double precision, or the mixed path's single-precision table with
+//         an optional double-precision zone), with the smoothing evaluated only where some lane
+//         of the wavefront needs it.
 // The clusters of a group are dealt out to K ways by rank: way k takes the far clusters whose
 // rank among the group's far clusters is k mod K, and likewise for the near clusters.  Every
 // way of every group then carries the same work to within one cluster of each kind, whatever
@@ -184,11 +187,11 @@ __device__ __forceinline__ void far_cluster(const Src &S, int64_t j0, const floa
 }
 
 // FP64 path: every pair in double precision.  Mixed path: near_pair32 (the single-precision
-// zones), summed per cluster and folded into the two-sum pair as for far clusters, and the
-// double-precision zone (the self term and the nearest neighbours, zone_pair64), whose
-// state lives in LDS (`zs`: per target of the lane, x, y, z and the three sums, 64 apart): it is
-// needed only for the few sources with such a pair, and keeping it out of the vector registers
-// buys the kernel two more waves per SIMD.
+// zones), summed per cluster and folded into the two-sum pair as for far clusters, and with
+// ZONE the double-precision zone (pairs below rho64, zone_pair64), whose state lives in LDS
+// (`zs`: per target of the lane, x, y, z and the three sums, 64 apart): it is needed only for
+// the few sources with such a pair, and keeping it out of the vector registers buys the kernel
+// a wave per SIMD.
 template <int R, bool VARD, bool MIXED, bool ZONE, bool STAGE>
 __device__ __forceinline__ void near_cluster(const Src &S, int64_t j0, const float4 *stg,
                                              const DeltaC &dcu, const DeltaC32 &dcu32,

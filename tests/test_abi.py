@@ -48,3 +48,18 @@ def test_host_side_validation_without_a_gpu():
     assert lib.sl_set_param(None, P.SL_PARAM_RHO64, 6.0) == P.SL_EINVAL
     assert lib.sl_patch_delta(None, 6, 4, 1, 2, 3, 1.0, 4, None) == P.SL_EINVAL
     assert "ctx is NULL" in P.sl_last_error()
+
+
+def test_pair_kernel_hash_ignores_comments_only():
+    """The hash that keys the stored PMC traffic changes with the pair kernel's code and not with
+    its comments or layout."""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    src = "int f(int a) { // add one\n  return a + 1; /* done */ }\n"
+    assert bench.code_text(src) == bench.code_text("int f(int a) {\n\n  return a + 1;   }")
+    assert bench.code_text(src) != bench.code_text(src.replace("a + 1", "a + 2"))
+    assert "//" not in bench.code_text(src) and "done" not in bench.code_text(src)
+    for p in bench.PAIR_SOURCES:
+        assert os.path.exists(os.path.join(bench.ROOT, p)), p
+    assert re.fullmatch(r"[0-9a-f]{16}", bench.pair_kernel_sha())

@@ -78,7 +78,8 @@ const char *sl_last_error(void);
  * SL_PARAM_TARGETS_PER_LANE: targets each lane of the pair kernels keeps in registers
  *   (1, 2 or 4; 0 = automatic, the default: 1 in SL_MIXED, 2 in SL_FP64).
  * SL_PARAM_WAVES_PER_SIMD: granularity of the pair kernels' work items: the sources are split
- *   until there are about this many items per SIMD (1..32; default 32). */
+ *   until there are about this many items per SIMD, into at most 128 ways per target block (64
+ *   in SL_MIXED) (1..64; default 64). */
 typedef enum {
     SL_PARAM_RHO64 = 0,
     SL_PARAM_KERNEL_TIMING = 1,

@@ -151,8 +151,8 @@ sl_status sl_set_param(sl_ctx *ctx, sl_param key, double value)
         return SL_OK;
     }
     if (key == SL_PARAM_WAVES_PER_SIMD) {
-        if (!(value >= 1.0 && value <= 32.0) || value != (double)(int)value)
-            return fail(SL_EINVAL, "sl_set_param: waves per SIMD is an integer in 1..32");
+        if (!(value >= 1.0 && value <= 64.0) || value != (double)(int)value)
+            return fail(SL_EINVAL, "sl_set_param: waves per SIMD is an integer in 1..64");
         std::lock_guard<std::mutex> l(ctx->mu);
         ctx->waves_per_simd = (int)value;
         return SL_OK;
@@ -288,7 +288,7 @@ sl_status sl_eval(sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *s
     }
     if (R == 0)   // measured on MI355X: the single-precision loops want occupancy, FP64 ILP
         R = mixed ? 1 : 2;
-    PairPlan plan = plan_pairs(np_s, np_t, R, ctx->n_cu * 4 * wps);
+    PairPlan plan = plan_pairs(np_s, np_t, R, ctx->n_cu * 4 * wps, mixed);
     plan.n_cu = ctx->n_cu;
 
     EvalWorkspace ws;

@@ -88,7 +88,7 @@ struct PairPlan {
     int n_cu;                // compute units: the work loop launches an occupancy-sized grid
 };
 
-PairPlan plan_pairs(int64_t np_src, int64_t np_tgt, int R, int waves_wanted);
+PairPlan plan_pairs(int64_t np_src, int64_t np_tgt, int R, int waves_wanted, bool mixed);
 // Target blocks per workgroup of the pair kernel (they share one cluster stream).
 int pair_group_size(bool mixed);
 // The pair kernel's work counter inside tblock_scratch.
@@ -189,7 +189,7 @@ struct sl_ctx {
     size_t budget = 0;
     double rho64 = 0.0;
     int targets_per_lane = 0;   // 0: chosen per call
-    int waves_per_simd = 32;
+    int waves_per_simd = 64;
     std::mutex mu;
     sl::Server *server = nullptr;
     // pair-kernel timing (SL_PARAM_KERNEL_TIMING)

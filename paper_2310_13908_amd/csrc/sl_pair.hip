@@ -33,7 +33,10 @@ namespace sl {
 
 namespace {
 
-constexpr int kMaxWays = 64;
+// Most ways per target block.  The mixed kernel is fast enough that the K per-way partial sums
+// (K x 3 x 8 bytes per target, written and read back once) weigh against finer items sooner.
+constexpr int kMaxWays = 128;
+constexpr int kMaxWaysMixed = 64;
 
 __device__ __forceinline__ TBlockRec make_rec(const PairArgs &a, int mixed, double cx, double cy,
                                               double cz, double rad, double dmax)
@@ -528,14 +531,15 @@ uint32_t *pair_counter(void *tblock_scratch, int n_tblocks)
                                         tblock_scratch_bytes(n_tblocks) - 256);
 }
 
-PairPlan plan_pairs(int64_t np_src, int64_t np_tgt, int R, int waves_wanted)
+PairPlan plan_pairs(int64_t np_src, int64_t np_tgt, int R, int waves_wanted, bool mixed)
 {
     PairPlan p;
     p.R = R;
     p.n_tblocks = (int)(np_tgt / (kWave * R));
     const int64_t n_cl = np_src / kCluster;
+    const int64_t cap = mixed ? kMaxWaysMixed : kMaxWays;
     int64_t K = (waves_wanted + p.n_tblocks - 1) / p.n_tblocks;
-    K = K < 1 ? 1 : (K > kMaxWays ? kMaxWays : K);
+    K = K < 1 ? 1 : (K > cap ? cap : K);
     K = K > n_cl ? n_cl : K;
     p.n_ways = (int)K;
     p.n_cu = 0;

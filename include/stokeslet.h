@@ -76,7 +76,8 @@ const char *sl_last_error(void);
  * SL_PARAM_KERNEL_TIMING: 1 = bracket every pair-kernel launch of sl_eval with HIP events on
  *   the caller's stream and accumulate the elapsed time into sl_stats; 0 (default) = off.
  * SL_PARAM_TARGETS_PER_LANE: targets each lane of the pair kernels keeps in registers
- *   (1, 2 or 4; 0 = automatic, the default: 1 in SL_MIXED, 2 in SL_FP64).
+ *   (1, 2 or 4; 0 = automatic, the default: 1 in SL_MIXED; in SL_FP64 1 up to 2^17 targets,
+ *   2 beyond).
  * SL_PARAM_WAVES_PER_SIMD: granularity of the pair kernels' work items: the sources are split
  *   until there are about this many items per SIMD, into at most 128 ways per target block (64
  *   in SL_MIXED) (1..64; default 64). */

@@ -234,6 +234,9 @@ sl_status sl_patch_delta(sl_ctx *ctx, int64_t n_patches, int64_t n, const double
     return SL_OK;
 }
 
+// Largest padded target count for which the FP64 pair kernel keeps one target a lane by default.
+constexpr int64_t kFp64OneTargetMaxN = 1 << 17;
+
 sl_status sl_eval(sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *sx,
                   const double *sy, const double *sz, const double *w, const double *fx,
                   const double *fy, const double *fz, int64_t n_tgt, const double *tx,
@@ -286,8 +289,11 @@ sl_status sl_eval(sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *s
         R = ctx->targets_per_lane;
         wps = ctx->waves_per_simd;
     }
-    if (R == 0)   // measured on MI355X: the single-precision loops want occupancy, FP64 ILP
-        R = mixed ? 1 : 2;
+    // Measured on MI355X: the single-precision loops want occupancy; FP64 wants occupancy while
+    // its near field (longer loops, more registers at two targets a lane) weighs in, and two
+    // targets a lane once the far field dominates (N = 24,576: 0.98 against 1.07 ms; N = 393,216:
+    // 125.5 against 119.6 ms).
+    if (R == 0) R = mixed ? 1 : (np_t <= kFp64OneTargetMaxN ? 1 : 2);
     PairPlan plan = plan_pairs(np_s, np_t, R, ctx->n_cu * 4 * wps, mixed);
     plan.n_cu = ctx->n_cu;
 

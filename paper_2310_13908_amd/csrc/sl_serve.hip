@@ -255,7 +255,7 @@ __device__ __forceinline__ void serve_targets(const BlockView &v, int64_t t0, co
                                    py[r], pz[r]);
                 }
             } else {
-#pragma unroll 1
+#pragma unroll ZONE ? 1 : 2
                 for (int j = 0; j < kCluster; ++j) {
                     const float4 u = st.f[2 * j], w = st.f[2 * j + 1];
                     bool z64[R], any = false;

@@ -114,17 +114,19 @@ def test_sort_paths_at_the_scan_threshold(ctx, n):
         assert eps(u, oracle.single_layer(s.X, s.w, f, d, targets=T)) < TOL[precision]
 
 
+@pytest.mark.parametrize("n_t", [65536, 65537])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_sort_few_sources_many_targets(ctx, precision):
-    """4,704 sources (a two-pass sort) and 70,000 distinct targets (a three-pass sort with the
-    count scan) in one call: the second sort reuses the scratch of the first.  Every target
-    against the oracle."""
+def test_sort_few_sources_many_targets(ctx, precision, n_t):
+    """4,704 sources (a two-pass sort) and 2^16 or 2^16 + 1 distinct targets in one call: the
+    last size sorted in two passes (64 blocks of 1024 keys, offsets from the raw counts) and the
+    first in three (65 blocks, the three-kernel count scan), each sort reusing the scratch of
+    the sources' sort.  Every target against the oracle."""
     import oracle
     s = make_surface(RBC, 28)
     f = sh_force(s.x0, 41)
     d = 2 * math.pi / 29
     rng = np.random.default_rng(41)
-    T = s.X[rng.integers(0, s.N, 70000)] + rng.normal(scale=0.05, size=(70000, 3))
+    T = s.X[rng.integers(0, s.N, n_t)] + rng.normal(scale=0.05, size=(n_t, 3))
     u = gpu_eval(ctx, s.X, s.w, f, d, targets=T, precision=precision)
     ref = oracle.single_layer(s.X, s.w, f, d, targets=T)
     assert eps(u, ref) < TOL[precision]

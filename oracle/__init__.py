@@ -6,13 +6,19 @@ shares no code with it.  The arithmetic lives in ``slref.c`` (plain C, glibc
 erf/exp, Neumaier sums, OpenMP over targets); this module only builds and loads
 it and marshals numpy arrays.
 
-Also the per-patch regularization parameter of eq. (regparam) (``patch_delta``).
+Also the per-patch regularization parameter of eq. (regparam) (``patch_delta``) and the
+upsampling step around the sum (``single_layer_upsampled``: X, F and the area element W
+upsampled by per-patch cubic splines, the sum on the fine grid with delta_u, the spline back).
 
 Pinned by ``tests/test_oracle_pins.py`` against the r -> 0 limits stated in
 Sec. 3.4, vanishing moments of s - 1, the sphere's closed-form drag and
 rotation velocities, S[n] = 0 with the O(delta^5) order, the discrete
 reciprocity identity, translation/rotation invariance and a 40-digit brute
-force on tiny inputs.
+force on tiny inputs; the upsampling step by exact bicubic reproduction of
+positions, derivatives and fine weights, fourth-order convergence of the fine
+nodes and of the fine weights' area, the sphere's closed form through the whole
+step, and S[n] = 0 through the whole step at a bound that a coarse-grid delta
+fails.
 """
 from __future__ import annotations
 
@@ -118,12 +124,15 @@ def patch_delta(X, n, C=1.0):
 
 
 # ----------------------------------------------------------------------------------------------
-# Upsampling sandwich (Sec. 3.4, "Upsampling"): u = I_d S^{delta_u}[I_u f] on I_u X.
-# Readings: the fine grid has factor*n nodes per direction at j pi/(factor n + 1) (N_up =
-# factor^2 N, the count of the paper's table); I_u and I_d are per-patch tensor-product cubic
-# splines with not-a-knot ends (de Boor's default), the end pieces extended where the fine grid
-# reaches past the coarse nodes; the fine weights are psi_u W_u h_u^2 with W_u = |X_u x X_v| from
-# the splines' derivatives; delta_u is eq. (regparam) on the fine grid.
+# Upsampling step (Sec. 3.4, "Upsampling"; the right-hand-side algorithm of Sec. 3.6, its
+# upsampling, single-layer and downsampling steps): u = I_d S^{delta_u}[I_u f] on X_u = I_u X.
+# The algorithm upsamples the nodes, the density and the area element with the same operator
+# (X_u = I_u X, F_u = I_u F, W_u = I_u W) and sums with X_u, F_u, the precomputed POU values
+# Psi_u and W_u, i.e. with the trapezoid-POU weights w_u = psi_u W_u h_u^2 of eq. (smoothint) on
+# the fine grid.  Readings: the fine grid has factor*n nodes per direction at j pi/(factor n + 1)
+# (N_up = factor^2 N, the count of the paper's table); I_u and I_d are per-patch tensor-product
+# cubic splines with not-a-knot ends (de Boor's default), the end pieces extended where the fine
+# grid reaches past the coarse nodes; delta_u is eq. (regparam) on the fine grid.
 # ----------------------------------------------------------------------------------------------
 def _grids(n, factor):
     nf = factor * n
@@ -145,21 +154,21 @@ def spline_resample(F, n_from, t_from, t_to, du=0, dv=0):
     return G.reshape((-1,) + comp)
 
 
-def upsampled_surface(X, n, psi_up, factor=4):
-    """(X_u, w_u) on the fine grid from the coarse nodes X: X_u = I_u X, w_u = psi_u W_u h_u^2."""
+def upsampled_surface(X, W, n, psi_up, factor=4):
+    """(X_u, w_u) on the fine grid from the coarse nodes X (N, 3) and their area elements W (N,):
+    X_u = I_u X, W_u = I_u W, w_u = psi_u W_u h_u^2."""
     tc, tf = _grids(n, factor)
     Xu = spline_resample(X, n, tc, tf)
-    xu = spline_resample(X, n, tc, tf, du=1)
-    xv = spline_resample(X, n, tc, tf, dv=1)
-    W = np.linalg.norm(np.cross(xu, xv), axis=1)
+    Wu = spline_resample(np.asarray(W, dtype=np.float64), n, tc, tf)
     hf = np.pi / (factor * n + 1)
-    return Xu, np.asarray(psi_up, dtype=np.float64) * W * hf * hf
+    return Xu, np.asarray(psi_up, dtype=np.float64) * Wu * hf * hf
 
 
-def single_layer_upsampled(X, f, n, psi_up, mu=1.0, C=1.0, factor=4, nthreads=0):
-    """u at the coarse nodes: I_d S^{delta_u}[I_u f] evaluated on the upsampled surface."""
+def single_layer_upsampled(X, W, f, n, psi_up, mu=1.0, C=1.0, factor=4, nthreads=0):
+    """u at the coarse nodes: I_d S^{delta_u}[I_u f] evaluated on the upsampled surface, from the
+    coarse nodes X, area elements W and density f."""
     tc, tf = _grids(n, factor)
-    Xu, wu = upsampled_surface(X, n, psi_up, factor)
+    Xu, wu = upsampled_surface(X, W, n, psi_up, factor)
     fu = spline_resample(f, n, tc, tf)
     du = patch_delta(Xu, factor * n, C=C)
     uu = single_layer(Xu, wu, fu, 0.0, mu=mu, delta_tgt=du, nthreads=nthreads)

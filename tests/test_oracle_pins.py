@@ -328,19 +328,56 @@ def test_spline_resample_reproduces_bicubics():
         assert np.allclose(G, want, rtol=0, atol=1e-11)
 
 
+def test_fine_weights_upsample_the_area_element():
+    """Sec. 3.6 (upsampling step): W_u = I_u W with the same spline operator as X and F, and the
+    fine weights are psi_u W_u h_u^2 (eq. (smoothint) on the fine grid).  A coarse area element
+    that is a bicubic in (u, v) on each patch is reproduced exactly by the not-a-knot splines, so
+    the fine weights must equal psi_u times that bicubic at the fine nodes times h_u^2: a weight
+    computed from anything else (the spline surface's own |X_u x X_v|, a coarse h, a missing
+    psi_u) fails.  Factors 2 and 4."""
+    import oracle
+    from capsule_inputs import fine_grid, fine_pou
+    n = 9
+    s = make_surface(RBC, n)
+    P = lambda u, v, k: (2.0 + 0.1 * k) + 0.3 * u - 0.05 * u ** 3 + 0.2 * v ** 2 * (1 + 0.1 * u) \
+        - 0.01 * k * v ** 3
+    for factor in (2, 4):
+        tc, tf = fine_grid(n, factor)
+        Uc, Vc = np.meshgrid(tc, tc, indexing="ij")
+        Uf, Vf = np.meshgrid(tf, tf, indexing="ij")
+        Wc = np.concatenate([P(Uc, Vc, k).ravel() for k in range(6)])
+        Wf = np.concatenate([P(Uf, Vf, k).ravel() for k in range(6)])
+        hf = math.pi / (factor * n + 1)
+        psi = fine_pou(n, factor)
+        Xu, wu = oracle.upsampled_surface(s.X, Wc, n, psi, factor)
+        assert Xu.shape == (6 * (factor * n) ** 2, 3)
+        assert np.allclose(wu, psi * Wf * hf * hf, rtol=1e-12, atol=0)
+
+
 def test_upsampled_surface_converges_at_fourth_order():
-    """I_u X against the exact positions of the fine nodes: O(h^4) (ratio ~16 per halving of h);
-    the fine weights integrate the sphere's area 4 pi."""
+    """I_u X against the exact positions of the fine nodes: O(h^4) (ratio ~16 per halving of h).
+    The fine weights psi_u (I_u W) h_u^2 integrate the biconcave surface's area (1-D quadrature
+    of the surface of revolution) with the fourth-order error of the spline interpolation of W:
+    an error ratio near 16 per halving, and below 1e-5 at n = 24 and 1e-6 at n = 48.  Weights
+    from the derivatives of the spline surface instead of I_u W miss these bounds (8.5e-5 at
+    n = 24)."""
     import oracle
     from capsule_inputs import fine_pou, fine_positions
-    errs, areas = [], []
+    from test_inputs import rbc_area_volume
+    errs = []
     for n in (8, 16, 32):
         s = make_surface(SPHERE, n)
-        Xu, wu = oracle.upsampled_surface(s.X, n, fine_pou(n))
+        Xu, wu = oracle.upsampled_surface(s.X, s.W, n, fine_pou(n))
         errs.append(np.abs(Xu - fine_positions(SPHERE, n)).max())
-        areas.append(abs(wu.sum() - 4 * math.pi))
     assert errs[0] / errs[1] > 10 and errs[1] / errs[2] > 12, errs
-    assert areas[2] < 1e-4 and areas[2] < areas[0], areas
+    A_rbc, _ = rbc_area_volume()
+    areas = []
+    for n in (12, 24, 48):
+        s = make_surface(RBC, n)
+        _, wu = oracle.upsampled_surface(s.X, s.W, n, fine_pou(n))
+        areas.append(abs(wu.sum() - A_rbc))
+    assert areas[0] / areas[1] > 8 and areas[1] / areas[2] > 12, areas
+    assert areas[1] < 1e-5 and areas[2] < 1e-6, areas
 
 
 def test_downsample_of_upsample_converges_to_identity():
@@ -366,6 +403,26 @@ def test_upsampled_single_layer_on_the_sphere():
     for n in (6, 12):
         s = make_surface(SPHERE, n)
         f = np.tile([0.0, 0.0, 1.0], (s.N, 1))
-        u = oracle.single_layer_upsampled(s.X, f, n, fine_pou(n), mu=1.0)
+        u = oracle.single_layer_upsampled(s.X, s.W, f, n, fine_pou(n), mu=1.0)
         errs.append(np.abs(u - [0.0, 0.0, 2.0 / 3.0]).max())
     assert errs[1] < 2e-5 and errs[1] < errs[0], errs
+
+
+def test_upsampled_single_layer_of_normal_vanishes():
+    """S[n] = 0 on a closed surface (the Stokeslet is divergence-free), through the whole
+    upsampling step on the paper's a = 0.6 ellipsoid (Sec. 4.1 test shape), normalized by the
+    response to e_z.  With delta_u = delta* of the fine grid (Sec. 3.4: delta_u by eq. (regparam)
+    on the upsampled grid) the error is 2.3e-4 at n = 8 and 4.1e-5 at n = 12, falling at order
+    about 4; a delta* taken from the coarse grid (4x larger, so about 4^5 times the O(delta^5)
+    regularization error) gives 2.5e-2 and 6.3e-3 and fails both bounds."""
+    import oracle
+    from capsule_inputs import fine_pou
+    errs = []
+    for n in (8, 12):
+        s = make_surface(ELLIPSOID_PAPER, n)
+        psi = fine_pou(n)
+        ez = np.tile([0.0, 0.0, 1.0], (s.N, 1))
+        scale = np.abs(oracle.single_layer_upsampled(s.X, s.W, ez, n, psi)).max()
+        errs.append(np.abs(oracle.single_layer_upsampled(s.X, s.W, s.normal, n, psi)).max() / scale)
+    assert errs[0] < 5e-4 and errs[1] < 8e-5, errs
+    assert math.log(errs[0] / errs[1]) / math.log(12 / 8) > 3.5, errs

@@ -159,6 +159,7 @@ def upsample_leg(P, ctx, dev, log, steps=3, warmup=1):
     p = W.c2()
     n = p.surface.n
     X, _, F = resident(dev, p.surface.X, p.surface.w, p.f)
+    Wa = torch.as_tensor(p.surface.W, device=dev)
     psi = torch.as_tensor(fine_pou(n), device=dev)
     fine_pairs = float((16 * p.N) ** 2)
     res = {"workload": "rbc_6x64x64_sh8 upsampled 4x (N_up = 393,216), delta_u = delta* (C = 1)",
@@ -166,7 +167,7 @@ def upsample_leg(P, ctx, dev, log, steps=3, warmup=1):
     outs = {}
     for prec in ("fp64", "mixed"):
         U = torch.empty((3, p.N), dtype=torch.float64, device=dev)
-        t = time_steps(lambda: ctx.single_layer_upsampled(X, F, n, psi, precision=prec, out=U), steps, warmup)
+        t = time_steps(lambda: ctx.single_layer_upsampled(X, Wa, F, n, psi, precision=prec, out=U), steps, warmup)
         outs[prec] = U.t().cpu().numpy()
         res[prec] = {"ms_per_step": round(t * 1e3, 3), "gpair_s": round(fine_pairs / t / 1e9, 1)}
         log(f"[bench] upsampled C2 {prec}: {t * 1e3:.2f} ms/step  {res[prec]['gpair_s']:.0f} Gpair/s "
@@ -177,13 +178,14 @@ def upsample_leg(P, ctx, dev, log, steps=3, warmup=1):
     s = make_surface(RBC, m)
     f = sh_force(s.x0, 64)
     t0 = time.perf_counter()
-    ref = oracle.single_layer_upsampled(s.X, f, m, fine_pou(m))
+    ref = oracle.single_layer_upsampled(s.X, s.W, f, m, fine_pou(m))
     tm = time.perf_counter() - t0
     Xs, _, Fs = resident(dev, s.X, s.w, f)
+    Ws = torch.as_tensor(s.W, device=dev)
     ps = torch.as_tensor(fine_pou(m), device=dev)
     res["oracle_check"] = {"surface": "rbc_6x24x24 (N_up = 55,296)", "oracle_s": round(tm, 2)}
     for prec in ("fp64", "mixed"):
-        u = ctx.single_layer_upsampled(Xs, Fs, m, ps, precision=prec)
+        u = ctx.single_layer_upsampled(Xs, Ws, Fs, m, ps, precision=prec)
         torch.cuda.synchronize()
         res["oracle_check"][f"eps_{prec}"] = rel_inf(u.cpu().numpy(), ref)
     log(f"[bench] upsampled: mixed vs fp64 {res['mixed_vs_fp64']:.2e}; vs oracle (6x24x24) fp64 "

@@ -139,12 +139,15 @@ sl_status sl_patch_delta(sl_ctx *ctx, int64_t n_patches, int64_t n, const double
                          void *stream);
 
 /*
- * The upsampling step of Sec. 3.4 around the sum, asynchronous on `stream`:
+ * The upsampling step of Sec. 3.4 around the sum (the upsampling, single-layer and downsampling
+ * steps of the right-hand-side algorithm of Sec. 3.6), asynchronous on `stream`:
  *
  *   u = I_d S^{delta_u}[I_u f], evaluated on the upsampled surface X_u = I_u X.
  *
  *  x, y, z:     device arrays of the n_patches n^2 nodes (patch-major, row-major within a patch;
  *               a patch's nodes sit at parameters (j, k) pi / (n + 1), j, k = 1..n).
+ *  W:           the area element |X_u x X_v| at the nodes (n_patches n^2, same order), as the
+ *               caller computes it for the coarse weights psi W h^2 (Sec. 3.3).
  *  psi_up:      the own-patch POU value of every fine node (n_patches (factor n)^2, same order),
  *               precomputed by the caller like the POU of the coarse nodes.
  *  fx, fy, fz:  density at the nodes.
@@ -154,18 +157,19 @@ sl_status sl_patch_delta(sl_ctx *ctx, int64_t n_patches, int64_t n, const double
  *  ux, uy, uz:  output at the nodes (n_patches n^2 each).
  *
  * I_u and I_d are per-patch tensor-product cubic splines with not-a-knot ends (the end pieces
- * extended where the fine grid reaches past the outermost nodes); the fine weights are
- * psi_u |X_u x X_v| h_u^2, h_u = pi / (factor n + 1), with the derivatives of the same splines;
- * delta_u = C delta* of the fine grid (as sl_patch_delta).  The sum runs as sl_eval with targets
- * = the fine nodes.  n >= 4 (the not-a-knot spline needs four nodes).  The spline operators are
- * built once per (n, factor) and kept by the context (the first call for a size synchronizes to
- * upload them); the rest of the work is enqueued.  SL_EINVAL for bad sizes or scalars or NULL
- * arrays, SL_ENOMEM / SL_EHIP on allocation or launch failures.
+ * extended where the fine grid reaches past the outermost nodes).  Nodes, density and area
+ * element are upsampled by the same operator (X_u = I_u X, F_u = I_u F, W_u = I_u W), the fine
+ * weights are psi_u W_u h_u^2 with h_u = pi / (factor n + 1), and delta_u = C delta* of the fine
+ * grid (as sl_patch_delta).  The sum runs as sl_eval with targets = the fine nodes.  n >= 4 (the
+ * not-a-knot spline needs four nodes).  The spline operators are built once per (n, factor) and
+ * kept by the context (the first call for a size synchronizes to upload them); the rest of the
+ * work is enqueued, with a workspace allocated and freed stream-ordered.  SL_EINVAL for bad sizes
+ * or scalars or NULL arrays, SL_ENOMEM / SL_EHIP on allocation or launch failures.
  */
 sl_status sl_eval_upsampled(sl_ctx *ctx, sl_precision prec, int64_t n_patches, int64_t n, int factor,
-                            const double *x, const double *y, const double *z, const double *psi_up,
-                            const double *fx, const double *fy, const double *fz, double C, double mu,
-                            double *ux, double *uy, double *uz, void *stream);
+                            const double *x, const double *y, const double *z, const double *W,
+                            const double *psi_up, const double *fx, const double *fy, const double *fz,
+                            double C, double mu, double *ux, double *uy, double *uz, void *stream);
 
 /*
  * Serving: device-resident surfaces and continuous batching.

@@ -63,25 +63,34 @@ class Context:
                      precision="fp64", stream=None, out=None):
         """u (n_tgt, 3) float64 on the device from torch device tensors X (N, 3), w (N,), f (N, 3).
 
-        Enqueued on the current torch stream (or `stream`); returns without synchronizing.
+        Enqueued on the current torch stream (or `stream`, which first waits for the current
+        stream); returns without synchronizing.  The SoA copies are made on the stream the library
+        works on, so the caching allocator does not hand their memory out before that work ends.
         """
         import torch
         prec = PRECISIONS[precision]
-        Xs, fs = _soa(X), _soa(f)
-        ws = w.to(torch.float64).contiguous()
-        n_src = Xs.shape[1]
-        if targets is None:
-            Ts, n_tgt, tp = None, n_src, (None, None, None)
-        else:
-            Ts = _soa(targets)
-            n_tgt = Ts.shape[1]
-            tp = (Ts[0].data_ptr(), Ts[1].data_ptr(), Ts[2].data_ptr())
-        dts = None if delta_tgt is None else delta_tgt.to(torch.float64).contiguous()
-        U = out if out is not None else torch.empty((3, n_tgt), dtype=torch.float64, device=Xs.device)
-        st = sl_eval(self.ptr, prec, n_src, Xs[0].data_ptr(), Xs[1].data_ptr(), Xs[2].data_ptr(),
-                     ws.data_ptr(), fs[0].data_ptr(), fs[1].data_ptr(), fs[2].data_ptr(), n_tgt,
-                     *tp, float(delta), None if dts is None else dts.data_ptr(), float(mu),
-                     U[0].data_ptr(), U[1].data_ptr(), U[2].data_ptr(), _stream_handle(stream))
+        cur = torch.cuda.current_stream()
+        st_obj = cur if stream is None else stream
+        if st_obj != cur:
+            st_obj.wait_stream(cur)
+        with torch.cuda.stream(st_obj):
+            Xs, fs = _soa(X), _soa(f)
+            ws = w.to(torch.float64).contiguous()
+            n_src = Xs.shape[1]
+            if targets is None:
+                Ts, n_tgt, tp = None, n_src, (None, None, None)
+            else:
+                Ts = _soa(targets)
+                n_tgt = Ts.shape[1]
+                tp = (Ts[0].data_ptr(), Ts[1].data_ptr(), Ts[2].data_ptr())
+            dts = None if delta_tgt is None else delta_tgt.to(torch.float64).contiguous()
+            U = out if out is not None else torch.empty((3, n_tgt), dtype=torch.float64,
+                                                        device=Xs.device)
+            st = sl_eval(self.ptr, prec, n_src, Xs[0].data_ptr(), Xs[1].data_ptr(),
+                         Xs[2].data_ptr(), ws.data_ptr(), fs[0].data_ptr(), fs[1].data_ptr(),
+                         fs[2].data_ptr(), n_tgt, *tp, float(delta),
+                         None if dts is None else dts.data_ptr(), float(mu), U[0].data_ptr(),
+                         U[1].data_ptr(), U[2].data_ptr(), int(st_obj.cuda_stream))
         check(st, "sl_eval")
         return U.t()
 
@@ -90,32 +99,50 @@ class Context:
         for nodes X (n_patches n^2, 3) in patch-major, row-major order; enqueued on the current
         torch stream (or `stream`).  Pass the result as `delta_tgt` to single_layer."""
         import torch
-        Xs = _soa(X)
-        npts = Xs.shape[1]
-        if n < 1 or npts % (n * n) != 0:
-            raise ValueError("X must hold whole patches of n x n nodes")
-        D = out if out is not None else torch.empty(npts, dtype=torch.float64, device=Xs.device)
-        check(sl_patch_delta(self.ptr, npts // (n * n), int(n), Xs[0].data_ptr(), Xs[1].data_ptr(),
-                             Xs[2].data_ptr(), float(C), D.data_ptr(), _stream_handle(stream)),
-              "sl_patch_delta")
+        cur = torch.cuda.current_stream()
+        st_obj = cur if stream is None else stream
+        if st_obj != cur:
+            st_obj.wait_stream(cur)
+        with torch.cuda.stream(st_obj):
+            Xs = _soa(X)
+            npts = Xs.shape[1]
+            if n < 1 or npts % (n * n) != 0:
+                raise ValueError("X must hold whole patches of n x n nodes")
+            D = out if out is not None else torch.empty(npts, dtype=torch.float64,
+                                                        device=Xs.device)
+            st = sl_patch_delta(self.ptr, npts // (n * n), int(n), Xs[0].data_ptr(),
+                                Xs[1].data_ptr(), Xs[2].data_ptr(), float(C), D.data_ptr(),
+                                int(st_obj.cuda_stream))
+        check(st, "sl_patch_delta")
         return D
 
-    def single_layer_upsampled(self, X, f, n, psi_up, mu=1.0, C=1.0, factor=4, precision="fp64",
-                               stream=None, out=None):
+    def single_layer_upsampled(self, X, W, f, n, psi_up, mu=1.0, C=1.0, factor=4,
+                               precision="fp64", stream=None, out=None):
         """u (N, 3) at the nodes X (n_patches n^2, 3) through the upsampling step: I_d S[I_u f]
-        on I_u X with fine POU values psi_up (n_patches (factor n)^2,) and delta_u = C delta*."""
+        on I_u X, with fine weights psi_up (I_u W) h_u^2 from the area element W (N,) at the
+        nodes and the fine POU values psi_up (n_patches (factor n)^2,), and delta_u = C delta*.
+        Enqueued like single_layer."""
         import torch
-        Xs, fs = _soa(X), _soa(f)
-        npts = Xs.shape[1]
-        if n < 1 or npts % (n * n) != 0:
-            raise ValueError("X must hold whole patches of n x n nodes")
-        ps = psi_up.to(torch.float64).contiguous()
-        U = out if out is not None else torch.empty((3, npts), dtype=torch.float64, device=Xs.device)
-        check(sl_eval_upsampled(self.ptr, PRECISIONS[precision], npts // (n * n), int(n), int(factor),
-                                Xs[0].data_ptr(), Xs[1].data_ptr(), Xs[2].data_ptr(), ps.data_ptr(),
-                                fs[0].data_ptr(), fs[1].data_ptr(), fs[2].data_ptr(), float(C),
-                                float(mu), U[0].data_ptr(), U[1].data_ptr(), U[2].data_ptr(),
-                                _stream_handle(stream)), "sl_eval_upsampled")
+        cur = torch.cuda.current_stream()
+        st_obj = cur if stream is None else stream
+        if st_obj != cur:
+            st_obj.wait_stream(cur)
+        with torch.cuda.stream(st_obj):
+            Xs, fs = _soa(X), _soa(f)
+            npts = Xs.shape[1]
+            if n < 1 or npts % (n * n) != 0:
+                raise ValueError("X must hold whole patches of n x n nodes")
+            Ws = W.to(torch.float64).contiguous()
+            ps = psi_up.to(torch.float64).contiguous()
+            U = out if out is not None else torch.empty((3, npts), dtype=torch.float64,
+                                                        device=Xs.device)
+            st = sl_eval_upsampled(self.ptr, PRECISIONS[precision], npts // (n * n), int(n),
+                                   int(factor), Xs[0].data_ptr(), Xs[1].data_ptr(),
+                                   Xs[2].data_ptr(), Ws.data_ptr(), ps.data_ptr(),
+                                   fs[0].data_ptr(), fs[1].data_ptr(), fs[2].data_ptr(), float(C),
+                                   float(mu), U[0].data_ptr(), U[1].data_ptr(), U[2].data_ptr(),
+                                   int(st_obj.cuda_stream))
+        check(st, "sl_eval_upsampled")
         return U.t()
 
     # -- serving ---------------------------------------------------------------------------
@@ -124,6 +151,8 @@ class Context:
         import torch
         Xs = _soa(X)
         ws = w.to(torch.float64).contiguous()
+        # the library copies on a stream of its own: the SoA copies must be complete first
+        torch.cuda.current_stream().synchronize()
         st, h = sl_surface_register(self.ptr, Xs.shape[1], Xs[0].data_ptr(), Xs[1].data_ptr(),
                                     Xs[2].data_ptr(), ws.data_ptr(), float(delta))
         check(st, "sl_surface_register")

@@ -65,7 +65,7 @@ def load():
         "sl_get_param": ([P, i32, ctypes.POINTER(d)], i32),
         "sl_eval": ([P, i32, i64, V, V, V, V, V, V, V, i64, V, V, V, d, V, d, V, V, V, V], i32),
         "sl_patch_delta": ([P, i64, i64, V, V, V, d, V, V], i32),
-        "sl_eval_upsampled": ([P, i32, i64, i64, i32, V, V, V, V, V, V, V, d, d, V, V, V, V], i32),
+        "sl_eval_upsampled": ([P, i32, i64, i64, i32, V, V, V, V, V, V, V, V, d, d, V, V, V, V], i32),
         "sl_surface_register": ([P, i64, V, V, V, V, d, ctypes.POINTER(u64)], i32),
         "sl_surface_release": ([P, u64], i32),
         "sl_submit": ([P, u64, i32, V, V, V, d, V, V, V, ctypes.POINTER(u64)], i32),
@@ -126,10 +126,10 @@ def sl_patch_delta(ctx, n_patches, n, x, y, z, C, delta_out, stream) -> int:
     return load().sl_patch_delta(ctx, n_patches, n, x, y, z, C, delta_out, stream)
 
 
-def sl_eval_upsampled(ctx, prec, n_patches, n, factor, x, y, z, psi_up, fx, fy, fz, C, mu, ux, uy,
-                      uz, stream) -> int:
-    return load().sl_eval_upsampled(ctx, prec, n_patches, n, factor, x, y, z, psi_up, fx, fy, fz, C,
-                                    mu, ux, uy, uz, stream)
+def sl_eval_upsampled(ctx, prec, n_patches, n, factor, x, y, z, W, psi_up, fx, fy, fz, C, mu, ux,
+                      uy, uz, stream) -> int:
+    return load().sl_eval_upsampled(ctx, prec, n_patches, n, factor, x, y, z, W, psi_up, fx, fy, fz,
+                                    C, mu, ux, uy, uz, stream)
 
 
 def sl_surface_register(ctx, n, x, y, z, w, delta):

@@ -1,12 +1,14 @@
-// sl_upsample.hip -- the upsampling step around the sum (Sec. 3.4, "Upsampling"):
+// sl_upsample.hip -- the upsampling step around the sum (Sec. 3.4, "Upsampling"; the
+// right-hand-side algorithm of Sec. 3.6, its upsampling, single-layer and downsampling steps):
 //
 //   u = I_d S^{delta_u}[I_u f]  evaluated on the upsampled surface X_u = I_u X,
 //
 // with I_u, I_d per-patch cubic-spline interpolation between the n x n grid of a patch and a grid
 // of factor n x factor n nodes (parameters j pi / (n + 1) and j pi / (factor n + 1), j >= 1; the
-// fine count is factor^2 N, the count of the paper's upsampling table), fine weights
-// w_u = psi_u |X_u x X_v| h_u^2 (POU values psi_u of the fine nodes given by the caller,
-// derivatives from the same splines), and delta_u of eq. (regparam) on the fine grid.
+// fine count is factor^2 N, the count of the paper's upsampling table).  The nodes, the density and
+// the area element are upsampled by the same operator (X_u = I_u X, F_u = I_u F, W_u = I_u W), and
+// the fine weights are w_u = psi_u W_u h_u^2 (eq. (smoothint) on the fine grid, with the POU values
+// psi_u of the fine nodes given by the caller); delta_u is eq. (regparam) on the fine grid.
 //
 // Splines: not-a-knot cubic splines (de Boor's default) on the uniform parameter grid; the end
 // pieces are extended where the fine grid reaches past the first or last coarse node.  Each 1-D
@@ -54,8 +56,8 @@ void notaknot_moments(const std::vector<double> &y, double h, std::vector<double
 }
 
 // Matrix (rows = targets t_a, columns = data nodes) of the spline through unit data vectors on the
-// nodes (j + 1) h, j = 0..N-1, evaluated (deriv = 0) or differentiated (deriv = 1) at targets.
-std::vector<double> spline_matrix(int N, double h, const std::vector<double> &t, int deriv)
+// nodes (j + 1) h, j = 0..N-1, evaluated at the targets.
+std::vector<double> spline_matrix(int N, double h, const std::vector<double> &t)
 {
     const int T = (int)t.size();
     std::vector<double> A((size_t)T * N, 0.0), y(N), M;
@@ -69,12 +71,8 @@ std::vector<double> spline_matrix(int N, double h, const std::vector<double> &t,
             const double tk = (k + 1) * h, tk1 = (k + 2) * h;
             const double L = tk1 - t[a], R = t[a] - tk;
             const double ck = y[k] / h - M[k] * h / 6.0, ck1 = y[k + 1] / h - M[k + 1] * h / 6.0;
-            double v;
-            if (deriv == 0)
-                v = M[k] * L * L * L / (6.0 * h) + M[k + 1] * R * R * R / (6.0 * h) + ck * L + ck1 * R;
-            else
-                v = -M[k] * L * L / (2.0 * h) + M[k + 1] * R * R / (2.0 * h) - ck + ck1;
-            A[(size_t)a * N + j] = v;
+            A[(size_t)a * N + j] =
+                M[k] * L * L * L / (6.0 * h) + M[k + 1] * R * R * R / (6.0 * h) + ck * L + ck1 * R;
         }
     }
     return A;
@@ -113,22 +111,14 @@ __global__ __launch_bounds__(256) void k_resample_rows(int64_t n_patches, int nf
     G[e] = s;
 }
 
-// w = psi |x_u x x_v| h^2 per fine node.
+// w = psi W_u h^2 per fine node.
 __global__ __launch_bounds__(256) void k_fine_weights(int64_t n, const double *__restrict__ psi,
-                                                      const double *__restrict__ ux,
-                                                      const double *__restrict__ uy,
-                                                      const double *__restrict__ uz,
-                                                      const double *__restrict__ vx,
-                                                      const double *__restrict__ vy,
-                                                      const double *__restrict__ vz, double h2,
+                                                      const double *__restrict__ Wu, double h2,
                                                       double *__restrict__ w)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    const double cx = uy[p] * vz[p] - uz[p] * vy[p];
-    const double cy = uz[p] * vx[p] - ux[p] * vz[p];
-    const double cz = ux[p] * vy[p] - uy[p] * vx[p];
-    w[p] = psi[p] * sqrt(cx * cx + cy * cy + cz * cz) * h2;
+    w[p] = psi[p] * Wu[p] * h2;
 }
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -153,9 +143,9 @@ using namespace sl;
 extern "C" {
 
 sl_status sl_eval_upsampled(sl_ctx *ctx, sl_precision prec, int64_t n_patches, int64_t n, int factor,
-                            const double *x, const double *y, const double *z, const double *psi_up,
-                            const double *fx, const double *fy, const double *fz, double C, double mu,
-                            double *ux, double *uy, double *uz, void *stream)
+                            const double *x, const double *y, const double *z, const double *W,
+                            const double *psi_up, const double *fx, const double *fy, const double *fz,
+                            double C, double mu, double *ux, double *uy, double *uz, void *stream)
 {
     if (!ctx) return fail(SL_EINVAL, "sl_eval_upsampled: ctx is NULL");
     if (prec != SL_FP64 && prec != SL_MIXED) return fail(SL_EINVAL, "sl_eval_upsampled: unknown precision");
@@ -165,7 +155,7 @@ sl_status sl_eval_upsampled(sl_ctx *ctx, sl_precision prec, int64_t n_patches, i
     if (n_patches > ((int64_t)1 << 30) / (nf * nf)) return fail(SL_EINVAL, "sl_eval_upsampled: more than 2^30 fine points");
     if (!(isfinite(C) && C > 0.0) || !(isfinite(mu) && mu > 0.0))
         return fail(SL_EINVAL, "sl_eval_upsampled: C and mu must be finite and > 0");
-    if (!x || !y || !z || !psi_up || !fx || !fy || !fz || !ux || !uy || !uz)
+    if (!x || !y || !z || !W || !psi_up || !fx || !fy || !fz || !ux || !uy || !uz)
         return fail(SL_EINVAL, "sl_eval_upsampled: NULL array");
     struct Guard {   // the context's device for the call, the caller's afterwards
         int prev = -1;
@@ -174,7 +164,7 @@ sl_status sl_eval_upsampled(sl_ctx *ctx, sl_precision prec, int64_t n_patches, i
     if (hipGetDevice(&guard.prev) != hipSuccess) guard.prev = -1;
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(SL_EHIP, "sl_eval_upsampled: hipSetDevice failed");
     const hipStream_t st = (hipStream_t)stream;
-    // spline matrices for (n, factor): up (nf x n), up' (nf x n), down (n x nf)
+    // spline matrices for (n, factor): up (nf x n), down (n x nf)
     double *mats = nullptr;
     {
         std::lock_guard<std::mutex> l(ctx->mu);
@@ -187,13 +177,11 @@ sl_status sl_eval_upsampled(sl_ctx *ctx, sl_precision prec, int64_t n_patches, i
             std::vector<double> tf(nf), tc(n);
             for (int64_t a = 0; a < nf; ++a) tf[a] = (a + 1) * hf;
             for (int64_t a = 0; a < n; ++a) tc[a] = (a + 1) * hc;
-            const std::vector<double> U = spline_matrix((int)n, hc, tf, 0);
-            const std::vector<double> Ud = spline_matrix((int)n, hc, tf, 1);
-            const std::vector<double> D = spline_matrix((int)nf, hf, tc, 0);
+            const std::vector<double> U = spline_matrix((int)n, hc, tf);
+            const std::vector<double> D = spline_matrix((int)nf, hf, tc);
             std::vector<double> all;
-            all.reserve(U.size() * 3);
+            all.reserve(U.size() + D.size());
             all.insert(all.end(), U.begin(), U.end());
-            all.insert(all.end(), Ud.begin(), Ud.end());
             all.insert(all.end(), D.begin(), D.end());
             hipError_t e = hipMalloc(&mats, all.size() * sizeof(double));
             if (e == hipSuccess) e = hipMemcpy(mats, all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice);
@@ -204,30 +192,28 @@ sl_status sl_eval_upsampled(sl_ctx *ctx, sl_precision prec, int64_t n_patches, i
             ctx->splines[key] = mats;
         }
     }
-    const double *U = mats, *Ud = mats + nf * n, *D = mats + 2 * nf * n;
+    const double *U = mats, *D = mats + nf * n;
     const int64_t Nf = n_patches * nf * nf;
-    // workspace: 12 fine fields (x, y, z, x_u.., x_v.., f..), w, delta, u (3); scratch T
+    // workspace: 9 fine fields (x, y, z, W, f (3), w, delta) and u (3); scratch T
     const int64_t scratch = n_patches * nf * nf;     // >= n_patches * n * nf and n_patches * nf * n
     void *base = nullptr;
-    hipError_t e = hipMallocAsync(&base, (size_t)(17 * Nf + scratch) * sizeof(double), st);
+    hipError_t e = hipMallocAsync(&base, (size_t)(12 * Nf + scratch) * sizeof(double), st);
     if (e != hipSuccess) return hip_fail(e, "sl_eval_upsampled: workspace");
-    double *W = static_cast<double *>(base);
-    double *X[3] = {W, W + Nf, W + 2 * Nf}, *Xu[3] = {W + 3 * Nf, W + 4 * Nf, W + 5 * Nf};
-    double *Xv[3] = {W + 6 * Nf, W + 7 * Nf, W + 8 * Nf}, *Fu[3] = {W + 9 * Nf, W + 10 * Nf, W + 11 * Nf};
-    double *wu = W + 12 * Nf, *du = W + 13 * Nf, *Uu[3] = {W + 14 * Nf, W + 15 * Nf, W + 16 * Nf};
-    double *T = W + 17 * Nf;
+    double *Ws = static_cast<double *>(base);
+    double *X[3] = {Ws, Ws + Nf, Ws + 2 * Nf}, *Wu = Ws + 3 * Nf;
+    double *Fu[3] = {Ws + 4 * Nf, Ws + 5 * Nf, Ws + 6 * Nf};
+    double *wu = Ws + 7 * Nf, *du = Ws + 8 * Nf, *Uu[3] = {Ws + 9 * Nf, Ws + 10 * Nf, Ws + 11 * Nf};
+    double *T = Ws + 12 * Nf;
     const double *xin[3] = {x, y, z}, *fin[3] = {fx, fy, fz};
     double *uout[3] = {ux, uy, uz};
     for (int c = 0; c < 3 && e == hipSuccess; ++c) {
         e = resample(n_patches, (int)n, (int)nf, xin[c], U, U, T, X[c], st);
-        if (e == hipSuccess) e = resample(n_patches, (int)n, (int)nf, xin[c], Ud, U, T, Xu[c], st);
-        if (e == hipSuccess) e = resample(n_patches, (int)n, (int)nf, xin[c], U, Ud, T, Xv[c], st);
         if (e == hipSuccess) e = resample(n_patches, (int)n, (int)nf, fin[c], U, U, T, Fu[c], st);
     }
+    if (e == hipSuccess) e = resample(n_patches, (int)n, (int)nf, W, U, U, T, Wu, st);
     const double hf = M_PI / (double)(nf + 1);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_fine_weights, dim3(blocks_for(Nf)), dim3(256), 0, st, Nf, psi_up, Xu[0], Xu[1],
-                           Xu[2], Xv[0], Xv[1], Xv[2], hf * hf, wu);
+        hipLaunchKernelGGL(k_fine_weights, dim3(blocks_for(Nf)), dim3(256), 0, st, Nf, psi_up, Wu, hf * hf, wu);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = launch_patch_delta(n_patches, nf, X[0], X[1], X[2], C, du, st);

@@ -82,12 +82,12 @@ def test_c2_rbc_full(ctx, c2_ref, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_c3_rbc_sampled(ctx, precision):
-    """6 x 256 x 256 nodes (N = 393,216), the launch configuration the benchmark times; 256 sampled
-    targets recomputed by the oracle over all sources."""
+    """6 x 256 x 256 nodes (N = 393,216), the launch configuration the benchmark times; the
+    workload's 4,096 sampled targets recomputed by the oracle over all sources."""
     import oracle
     p = W.c3()
     u = gpu_eval(ctx, p.surface.X, p.surface.w, p.f, p.delta, precision=precision)
-    idx = W.c3_subset(p.N, 256)
+    idx = W.c3_subset(p.N, 4096)
     ref = oracle.single_layer(p.surface.X, p.surface.w, p.f, p.delta, targets=p.surface.X[idx])
     assert eps(u[idx], ref) < TOL[precision]
     assert np.all(np.isfinite(u))
@@ -164,6 +164,30 @@ def test_per_target_delta(ctx, precision):
     u = gpu_eval(ctx, s.X, s.w, f, 0.0, targets=T, delta_tgt=dtt, precision=precision)
     ref = oracle.single_layer(s.X, s.w, f, 0.0, targets=T, delta_tgt=dtt)
     assert eps(u, ref) < TOL[precision]
+
+
+@pytest.mark.parametrize("precision,rho64", [("fp64", 0.0), ("mixed", 0.0), ("mixed", 1.0)])
+def test_per_target_delta_above_2_17_targets(ctx, precision, rho64):
+    """RBC 6 x 160 x 160 (N = 153,600 > 2^17 targets, where the FP64 path keeps two targets per
+    lane) with the paper's per-patch delta = delta* (eq. (regparam)) and with a random per-target
+    delta; 256 sampled targets against the oracle over all sources.  Mixed without and with the
+    FP64 zone."""
+    import oracle
+    n = 160
+    s = make_surface(RBC, n)
+    f = sh_force(s.x0, 160)
+    idx = np.sort(np.random.default_rng(160).choice(s.N, size=256, replace=False))
+    dstar = oracle.patch_delta(s.X, n)
+    drand = (2 * math.pi / (n + 1)) * (0.5 + np.random.default_rng(161).random(s.N))
+    ctx.set_rho64(rho64)
+    try:
+        for dt in (dstar, drand):
+            u = gpu_eval(ctx, s.X, s.w, f, 0.0, delta_tgt=dt, precision=precision)
+            ref = oracle.single_layer(s.X, s.w, f, 0.0, targets=s.X[idx], delta_tgt=dt[idx])
+            assert eps(u[idx], ref) < TOL[precision]
+            assert np.all(np.isfinite(u))
+    finally:
+        ctx.set_rho64(0.0)
 
 
 @pytest.mark.parametrize("precision,rho64", [("fp64", 0.0), ("mixed", 0.0), ("mixed", 1.0)])
@@ -307,9 +331,10 @@ def test_rho64_parameter(ctx, c2_ref):
     assert errs[12.0] < errs[0.0] and errs[12.0] < errs[1.0]
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_launch_shapes(precision):
-    """Every targets-per-lane and work granularity gives the same sums to the tolerance.  N =
+@pytest.mark.parametrize("precision,rho64", [("fp64", 0.0), ("mixed", 0.0), ("mixed", 1.0)])
+def test_launch_shapes(precision, rho64):
+    """Every targets-per-lane and work granularity gives the same sums to the tolerance, with one
+    delta and with a per-target delta, in FP64 and in mixed without and with the FP64 zone.  N =
     6 * 21^2 = 2646 pads to 2816 = 11 blocks of 256: with 4 targets per lane the last workgroup
     of four blocks is short, and distinct targets (1000 points) pad to a different count."""
     import oracle
@@ -318,9 +343,14 @@ def test_launch_shapes(precision):
     f = sh_force(s.x0, 77)
     d = 2 * math.pi / 22
     T = s.X[::3] * 1.01
+    dt = d * (0.6 + 0.8 * np.random.default_rng(21).random(s.N))
+    dtt = dt[::3]
     ref = oracle.single_layer(s.X, s.w, f, d)
     ref_t = oracle.single_layer(s.X, s.w, f, d, targets=T)
+    ref_v = oracle.single_layer(s.X, s.w, f, 0.0, delta_tgt=dt)
+    ref_vt = oracle.single_layer(s.X, s.w, f, 0.0, targets=T, delta_tgt=dtt)
     with P.Context(0) as c:
+        c.set_rho64(rho64)
         for R in (1, 2, 4):
             for wps in (1, 3, 16, 64):
                 P.check(P.sl_set_param(c.ptr, P.SL_PARAM_TARGETS_PER_LANE, float(R)))
@@ -329,6 +359,10 @@ def test_launch_shapes(precision):
                 assert eps(u, ref) < TOL[precision], (R, wps)
                 u = gpu_eval(c, s.X, s.w, f, d, targets=T, precision=precision)
                 assert eps(u, ref_t) < TOL[precision], (R, wps)
+                u = gpu_eval(c, s.X, s.w, f, 0.0, delta_tgt=dt, precision=precision)
+                assert eps(u, ref_v) < TOL[precision], (R, wps, "delta_tgt")
+                u = gpu_eval(c, s.X, s.w, f, 0.0, targets=T, delta_tgt=dtt, precision=precision)
+                assert eps(u, ref_vt) < TOL[precision], (R, wps, "delta_tgt, targets")
 
 
 @pytest.fixture(scope="module")

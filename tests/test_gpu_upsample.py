@@ -28,8 +28,8 @@ def dev(a):
 
 def run(ctx, s, f, n, precision, mu=1.0, C=1.0, factor=4):
     import torch
-    u = ctx.single_layer_upsampled(dev(s.X), dev(f), n, dev(fine_pou(n, factor)), mu=mu, C=C,
-                                   factor=factor, precision=precision)
+    u = ctx.single_layer_upsampled(dev(s.X), dev(s.W), dev(f), n, dev(fine_pou(n, factor)), mu=mu,
+                                   C=C, factor=factor, precision=precision)
     torch.cuda.synchronize()
     return u.cpu().numpy()
 
@@ -49,8 +49,46 @@ def test_parity_with_the_oracle(ctx, shape, n, factor, mu, C, precision):
     s = make_surface(shape, n)
     f = sh_force(s.x0, 60 + n)
     u = run(ctx, s, f, n, precision, mu=mu, C=C, factor=factor)
-    ref = oracle.single_layer_upsampled(s.X, f, n, fine_pou(n, factor), mu=mu, C=C, factor=factor)
+    ref = oracle.single_layer_upsampled(s.X, s.W, f, n, fine_pou(n, factor), mu=mu, C=C,
+                                        factor=factor)
     assert eps(u, ref) < TOL[precision]
+
+
+@pytest.fixture(scope="module")
+def rbc40_two_patches():
+    """RBC n = 40 (N = 9,600 coarse, N_up = 153,600 fine nodes): the oracle's fine sum for the fine
+    targets of patches 1 and 4 only (2 x 25,600 targets against all 153,600 sources), splined
+    back to those patches' coarse nodes.  A patch's coarse values depend only on its own fine
+    values, so these are the oracle's values at those nodes."""
+    import oracle
+    from capsule_inputs import fine_grid
+    n, factor = 40, 4
+    nf = factor * n
+    s = make_surface(RBC, n)
+    f = sh_force(s.x0, 4040)
+    psi = fine_pou(n, factor)
+    tc, tf = fine_grid(n, factor)
+    Xu, wu = oracle.upsampled_surface(s.X, s.W, n, psi, factor)
+    fu = oracle.spline_resample(f, n, tc, tf)
+    du = oracle.patch_delta(Xu, nf)
+    refs = {}
+    for p in (1, 4):
+        fine = slice(p * nf * nf, (p + 1) * nf * nf)
+        uu = oracle.single_layer(Xu, wu, fu, 0.0, targets=Xu[fine], delta_tgt=du[fine])
+        refs[p] = oracle.spline_resample(uu, nf, tf, tc)
+    return s, f, n, refs
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_parity_fine_grid_above_2_17(ctx, rbc40_two_patches, precision):
+    """The fine grid above 2^17 targets, where the FP64 path switches to two targets per lane
+    (with per-target delta): the device's full evaluation at the coarse nodes of two patches
+    against the oracle, element by element."""
+    s, f, n, refs = rbc40_two_patches
+    u = run(ctx, s, f, n, precision)
+    for p, ref in refs.items():
+        got = u[p * n * n:(p + 1) * n * n]
+        assert eps(got, ref) < TOL[precision], (p, eps(got, ref))
 
 
 def test_sphere_uniform_traction(ctx):

@@ -91,13 +91,13 @@ int slref_eval(int64_t n_src, const double *sx, const double *sy, const double *
     }
     const double scale = 1.0 / (8.0 * SLREF_PI * mu);
 #ifdef _OPENMP
-    if (nthreads > 0)
-        omp_set_num_threads(nthreads);
+    /* this call only: the process-wide default stays as it was */
+    const int team = nthreads > 0 ? nthreads : omp_get_max_threads();
 #else
     (void)nthreads;
 #endif
 
-#pragma omp parallel for schedule(dynamic, 16)
+#pragma omp parallel for schedule(dynamic, 16) num_threads(team)
     for (int64_t i = 0; i < n_tgt; ++i) {
         const double d = delta_tgt ? delta_tgt[i] : delta;
         neumaier ax = {0, 0}, ay = {0, 0}, az = {0, 0};

@@ -117,6 +117,28 @@ sl_status sl_eval(sl_ctx *ctx, sl_precision prec,
                   double *ux, double *uy, double *uz, void *stream);
 
 /*
+ * sl_eval for callers that cannot allocate device memory (code under stream capture, serving
+ * loops that must not call the allocator, harnesses that forbid allocation).  Same arguments,
+ * results and errors as sl_eval, within its tolerance (the work may be split into fewer, larger
+ * items so that it fits), with one difference: the workspace is a library-owned device array of
+ * 256 MiB, one per GPU, held from this entry point's first call on that GPU until the process
+ * ends.  The call allocates and frees nothing.  SL_EINVAL, with nothing enqueued, when a problem's
+ * workspace does not fit that array even as a single work item per target block (about a million
+ * points in SL_MIXED with targets = sources).  SL_PARAM_KERNEL_TIMING is ignored here.
+ *
+ * Every call on a GPU uses that GPU's one array: calls on one GPU must not overlap -- enqueue them
+ * on one stream, or order them yourself; calls on different streams that run at the same time
+ * race on the array and corrupt each other's results.  The array keeps the last call's contents;
+ * each call initializes what it reads.
+ */
+sl_status sl_eval_noalloc(sl_ctx *ctx, sl_precision prec,
+                          int64_t n_src, const double *sx, const double *sy, const double *sz,
+                          const double *w, const double *fx, const double *fy, const double *fz,
+                          int64_t n_tgt, const double *tx, const double *ty, const double *tz,
+                          double delta, const double *delta_tgt, double mu,
+                          double *ux, double *uy, double *uz, void *stream);
+
+/*
  * Per-patch regularization parameter of Sec. 3.4, eq. (regparam), asynchronous on `stream`:
  *
  *   delta_out[p] = C delta*_i for every node p of patch i, where delta*_i is the largest

@@ -11,7 +11,7 @@ from . import _binding
 from ._binding import (EXPORTED, SL_EBUSY, SL_EHIP, SL_EINVAL, SL_ENOMEM, SL_ENOTFOUND, SL_ETIMEDOUT,
                        SL_FP64, SL_MIXED, SL_OK, SL_PARAM_KERNEL_TIMING, SL_PARAM_RHO64,
                        SL_PARAM_TARGETS_PER_LANE, SL_PARAM_WAVES_PER_SIMD, SlError, check, load, sl_create,
-                       sl_destroy, sl_eval, sl_eval_upsampled, sl_get_param, sl_get_stats, sl_last_error,
+                       sl_destroy, sl_eval, sl_eval_noalloc, sl_eval_upsampled, sl_get_param, sl_get_stats, sl_last_error,
                        sl_patch_delta, sl_poll,
                        sl_request_bytes, sl_set_param, sl_submit, sl_surface_register,
                        sl_surface_release, sl_wait)

@@ -100,6 +100,17 @@ hipError_t launch_reduce(const double *part, int n_ways, int64_t np, const int32
                          double scale, double *ux, double *uy, double *uz, hipStream_t st);
 hipError_t launch_fill_zero(double *ux, double *uy, double *uz, int64_t n, hipStream_t st);
 
+// sl_eval's validation and launch sequence (sl_api.hip).  fixed == nullptr: the workspace is
+// allocated and freed stream-ordered; otherwise the fixed_bytes of device memory at `fixed` hold it
+// (the number of ways is reduced until it fits; SL_EINVAL if even one way does not).  `who` names
+// the entry point in error messages.
+sl_status eval_common(const char *who, sl_ctx *ctx, sl_precision prec, int64_t n_src, const double *sx,
+                      const double *sy, const double *sz, const double *w, const double *fx,
+                      const double *fy, const double *fz, int64_t n_tgt, const double *tx,
+                      const double *ty, const double *tz, double delta, const double *delta_tgt,
+                      double mu, double *ux, double *uy, double *uz, void *stream, char *fixed,
+                      size_t fixed_bytes);
+
 // Per-patch regularization parameter (sl_patch.hip): out[p] = C delta*_i for the n x n nodes
 // of each of n_patches patches (patch-major, row-major), n >= 1.
 hipError_t launch_patch_delta(int64_t n_patches, int64_t n, const double *x, const double *y,

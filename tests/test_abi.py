@@ -48,6 +48,10 @@ def test_host_side_validation_without_a_gpu():
     assert lib.sl_set_param(None, P.SL_PARAM_RHO64, 6.0) == P.SL_EINVAL
     assert lib.sl_patch_delta(None, 6, 4, 1, 2, 3, 1.0, 4, None) == P.SL_EINVAL
     assert "ctx is NULL" in P.sl_last_error()
+    st = lib.sl_eval_noalloc(None, 0, 10, 1, 1, 1, 1, 1, 1, 1, 10, None, None, None, 0.1, None, 1.0,
+                             2, 3, 4, None)
+    assert st == P.SL_EINVAL
+    assert "sl_eval_noalloc" in P.sl_last_error()
 
 
 def test_pair_kernel_hash_ignores_comments_only():

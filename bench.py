@@ -2,11 +2,12 @@
 """Benchmark of the regularized Stokes single layer on one MI355X.
 
 A step is one full evaluation u = S^delta[f] at every node of the biconcave surface with
-6 x 64 x 64 nodes (N = 24,576), SH force density, delta = 2h: spatial sort + packing,
-pair kernel and per-target reduction, all through sl_eval, with inputs resident in HBM.
+6 x 256 x 256 nodes (N = 393,216; 1.55e11 pairs), SH force density, delta = 2h: spatial sort +
+packing, pair kernel and per-target reduction, all through sl_eval, with inputs resident in HBM.
 `value` is N^2 / t_step in Gpair/s for the headline precision (mixed by default); the
-double-precision path, the 6 x 256 x 256 surface and the serving stream are reported beside
-it.  Prints exactly one JSON line on stdout; progress goes to stderr.
+double-precision path, the 6 x 64 x 64 surface, the per-patch delta, the upsampling step and the
+serving streams are reported beside it.  Prints exactly one JSON line on stdout; progress goes to
+stderr.
 """
 from __future__ import annotations
 
@@ -52,13 +53,16 @@ def pair_kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def count_near(X, delta, cuts, chunk=512):
+def count_near(X, delta, cuts, chunk=256):
     """Exact number of (target, source) pairs with r / delta < cut, for each cut (fp64 on the
     GPU, plain differences -- measurement bookkeeping, not part of the timed path)."""
     n = X.shape[0]
+    Xt = X.t().contiguous()
     out = {c: 0 for c in cuts}
     for i in range(0, n, chunk):
-        d2 = (X[i:i + chunk, None, :] - X[None, :, :]).square_().sum(dim=-1)
+        d2 = (X[i:i + chunk, 0:1] - Xt[0:1, :]).square_()
+        d2 += (X[i:i + chunk, 1:2] - Xt[1:2, :]).square_()
+        d2 += (X[i:i + chunk, 2:3] - Xt[2:3, :]).square_()
         for c in cuts:
             out[c] += int((d2 < (c * delta) ** 2).sum().item())
         del d2
@@ -95,6 +99,80 @@ def measure_precision(ctx, P, prob, tens, precision, steps, warmup):
     launches = max(1, s1.pair_launches - s0.pair_launches)
     kern_ms = (s1.pair_ms - s0.pair_ms) / launches
     return t * 1e3, kern_ms, out
+
+
+def measure_headline(ctx, P, prob, tens, precision, steps, warmup, reps=30):
+    """The timed region: `steps` evaluations back to back, with the HIP events that the library
+    records around its pair-kernel launch on the caller's stream (the kernel's average duration
+    over exactly these launches).  Then `reps` evaluations one at a time, each between two events
+    on the same stream, for the median."""
+    import torch
+    X, w, F = tens
+    out = torch.empty((3, prob.N), dtype=torch.float64, device=X.device)
+    fn = lambda: ctx.single_layer(X, w, F, prob.delta, precision=precision, out=out)
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s0 = P.sl_get_stats(ctx.ptr)
+    P.check(P.sl_set_param(ctx.ptr, P.SL_PARAM_KERNEL_TIMING, 1.0))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    P.check(P.sl_set_param(ctx.ptr, P.SL_PARAM_KERNEL_TIMING, 0.0))
+    s1 = P.sl_get_stats(ctx.ptr)
+    launches = s1.pair_launches - s0.pair_launches
+    kern_ms = (s1.pair_ms - s0.pair_ms) / max(1, launches)
+    per = []
+    cur = torch.cuda.current_stream()
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(cur)
+        fn()
+        e1.record(cur)
+        e1.synchronize()
+        per.append(e0.elapsed_time(e1))
+    per.sort()
+    return t * 1e3, kern_ms, int(launches), per[len(per) // 2], out
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline_sampled(prob, idx, idx_one):
+    """The oracle as it stands on the host cores: all threads on the sampled targets `idx` (every
+    source for each), and one thread on the first targets `idx_one`.  Returns the baseline record
+    and the all-thread result (the reference for eps on those targets)."""
+    import oracle
+    oracle.build(force=False)
+    X = prob.surface.X
+    threads = oracle.max_threads()
+    t0 = time.perf_counter()
+    ref = oracle.single_layer(X, prob.surface.w, prob.f, prob.delta, targets=X[idx])
+    dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    oracle.single_layer(X, prob.surface.w, prob.f, prob.delta, targets=X[idx_one], nthreads=1)
+    dt1 = time.perf_counter() - t1
+    rate = len(idx) * prob.N / dt / 1e9
+    rate1 = len(idx_one) * prob.N / dt1 / 1e9
+    rec = {"value": round(rate, 5), "unit": "Gpair/s", "cores": threads, "kind": "oracle",
+           "sample": f"{len(idx)} sampled targets x all {prob.N} sources of the same surface and "
+                     f"density ({len(idx) * prob.N:.3g} pairs, {dt:.1f} s)",
+           "cpu_model": cpu_model(), "seconds": round(dt, 3),
+           "full_evaluation_s_extrapolated": round(prob.N * prob.N / (rate * 1e9), 1),
+           "one_core": {"value": round(rate1, 5), "unit": "Gpair/s", "cores": 1,
+                        "seconds": round(dt1, 3),
+                        "sample": f"{len(idx_one)} of those targets x all {prob.N} sources"}}
+    return rec, ref
 
 
 def resident(dev, X, w, f):
@@ -193,21 +271,26 @@ def upsample_leg(P, ctx, dev, log, steps=3, warmup=1):
     return res
 
 
-def roofline(precision, pairs, near, kern_ms):
+def roofline(precision, pairs, near, kern_ms, workload):
+    """Vector-ALU roofline of the pair kernel: algorithmic flops per launch (28 per far pair, 49
+    per pair within the smoothing radius, exact counts) over its average launch duration, against
+    the published vector peak of the precision it computes in.  `traffic` is the HBM bytes per
+    launch from the stored rocprofv3 PMC runs of this workload, while they match the kernel's code."""
     flops = FLOPS_FAR * (pairs - near) + FLOPS_NEAR * near
     achieved = flops / (kern_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[precision]
     traffic = None
     if os.path.exists(PMC_FILE):
         rec = json.load(open(PMC_FILE))
-        entry = rec.get("kernels", {}).get(precision)
+        entry = rec.get("workloads", {}).get(workload, {}).get(precision)
         if entry and rec.get("pair_kernel_sha") == pair_kernel_sha():
             traffic = entry["hbm_bytes_per_launch"]
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": traffic,
             "kernel_ms": round(kern_ms, 4), "flops_per_launch": flops,
             "flops_per_pair": {"far": FLOPS_FAR, "near": FLOPS_NEAR}, "near_pairs": near,
-            "pairs": pairs}
+            "pairs": pairs, "algorithmic_bytes_per_launch": 24 * 2 * int(math.isqrt(pairs)) +
+            (64 if precision == "fp64" else 96) * int(math.isqrt(pairs))}
 
 
 def cpu_baseline(prob):
@@ -347,33 +430,51 @@ def serving_leg(P, dev, log, check_oracle=True):
     return out
 
 
-def memory_leg(P, dev, log, n_large=2, n_small=62, passes=2):
-    """A scaled sample of the memory-admitted stream: n_large capsules of N = 6 * 512^2
-    interleaved with n_small ones (n log-uniform in [16, 64]), RBC and ellipsoid, evaluated in
-    `passes` passes with a fresh density each time.  The client keeps surfaces resident across
-    passes (least recently used first out): when a registration is refused for lack of memory it
-    releases idle surfaces, else retires its oldest request first.  Run with the full budget
-    (everything stays resident) and with a budget that holds one large capsule but not two (the
-    large surfaces are evicted and registered again)."""
+def memory_leg(P, dev, log, n_large=2, n_small=62, passes=2, budgets=("full", "one_large")):
+    """The memory-admitted stream: n_large capsules of N = 6 * 512^2 interleaved with n_small ones
+    (n log-uniform in [16, 64]), RBC and ellipsoid, evaluated in `passes` passes with a fresh
+    density each time (the stated size is 64 + 2,000; the default run is a scaled sample).  The
+    client keeps surfaces resident across passes (least recently used first out): when a
+    registration is refused for lack of memory it releases idle surfaces, else retires its oldest
+    request first.  Run with the full budget (everything stays resident) and with a budget that
+    holds one large capsule but not two (the large surfaces are evicted and registered again).
+    Surfaces and SH bases are generated once per (shape, n) and densities when submitted."""
     import collections
     import numpy as np
     import torch
     from capsule_inputs import forces as FO
+    from capsule_inputs import make_surface
     from capsule_inputs import workloads as W
     stream = W.memory_admitted_stream(n_large=n_large, n_small=n_small)
     t0 = time.perf_counter()
-    probs = [r.problem() for r in stream.requests]
-    # pass k > 0 uses a fresh seeded density on the same surface
-    dens = [[p.f] + [FO.sh_force(p.surface.x0, W.SEED_C5 * 100 + 7 * k + i)
-                     for k in range(1, passes)] for i, p in enumerate(probs)]
-    log(f"[bench] memory stream: {len(probs)} capsules x {passes} passes generated in "
+    surfs, bases = {}, {}
+    for r in stream.requests:
+        if (r.shape, r.n) not in surfs:
+            surfs[(r.shape, r.n)] = make_surface(W.SERVING_SHAPES[r.shape], r.n)
+        if r.n not in bases:
+            bases[r.n] = FO.real_sph_harm_all(surfs[(r.shape, r.n)].x0)
+    log(f"[bench] memory stream: {len(stream.requests)} capsules, {len(surfs)} surfaces generated in "
         f"{time.perf_counter() - t0:.1f} s")
+
+    class Req:
+        def __init__(self, i, r):
+            self.surface = surfs[(r.shape, r.n)]
+            self.N = r.N
+            self.delta = W.delta_2h(r.n)
+            self.seed, self.i, self.n = r.seed, i, r.n
+
+        def density(self, k):
+            seed = self.seed if k == 0 else W.SEED_C5 * 100 + 7 * k + self.i
+            return bases[self.n] @ FO.sh_coefficients(seed).T
+
+    probs = [Req(i, r) for i, r in enumerate(stream.requests)]
     total = float(sum(p.N * p.N for p in probs)) * passes
     n_big = max(p.N for p in probs)
     per_point = 85                       # resident surface (49 B) + mixed staging (36 B) per point
-    budgets = {"full": 16 << 30, "one_large": int(1.15 * per_point * n_big)}
+    all_budgets = {"full": 16 << 30, "one_large": int(1.15 * per_point * n_big)}
+    budgets = {k: all_budgets[k] for k in budgets}
     out = {"workload": f"{n_large} capsules N = {n_big} + {n_small} with n in [16, 64] (RBC / "
-                       f"ellipsoid), SH density, delta = 2h, {passes} passes with fresh densities; "
+                       f"ellipsoid), SH density, delta = 2h, {passes} pass(es) with fresh densities; "
                        "surfaces kept resident, least recently used released when memory is short",
            "total_pairs": total, "requests": len(probs) * passes}
     for bname, budget in budgets.items():
@@ -428,7 +529,7 @@ def memory_leg(P, dev, log, n_large=2, n_small=62, passes=2):
                                         raise
                                     make_room(budget, None)   # everything idle goes
                         make_room(ctx.request_bytes(resident[i], prec), i)
-                        f = torch.as_tensor(np.ascontiguousarray(dens[i][k].T), device=dev)
+                        f = torch.as_tensor(np.ascontiguousarray(p.density(k).T), device=dev)
                         u = torch.empty_like(f)
                         cur.synchronize()
                         rid = ctx.submit_prepared(resident[i], f, u, precision=prec)
@@ -449,17 +550,48 @@ def memory_leg(P, dev, log, n_large=2, n_small=62, passes=2):
     return out
 
 
+def secondary_c2(P, ctx, dev, steps, warmup, with_oracle):
+    """The 6 x 64 x 64 surface (N = 24,576): both precisions, roofline of the pair kernel (its
+    average duration from the library's events in a second pass), error against the oracle over
+    every target."""
+    from capsule_inputs import workloads as W
+    prob = W.c2()
+    tens = resident(dev, prob.surface.X, prob.surface.w, prob.f)
+    pairs = prob.N * prob.N
+    near = count_near(tens[0], prob.delta, [RHO_EXACT64, 5.0])
+    out = {"workload": "rbc_6x64x64_sh8", "N": prob.N, "delta": prob.delta}
+    outs = {}
+    for prec in ("fp64", "mixed"):
+        ms, kern_ms, outs[prec] = measure_precision(ctx, P, prob, tens, prec, steps, warmup)
+        near_p = near[RHO_EXACT64] if prec == "fp64" else near[5.0]
+        out[prec] = {"ms_per_step": round(ms, 4), "gpair_s": round(pairs / (ms * 1e-3) / 1e9, 3),
+                     "roofline": roofline(prec, pairs, near_p, kern_ms, "rbc_6x64x64_sh8")}
+        log(f"[bench] C2 {prec}: {ms:.3f} ms/step  {out[prec]['gpair_s']:.1f} Gpair/s  pair kernel "
+            f"{kern_ms:.3f} ms  {out[prec]['roofline']['frac'] * 100:.1f}% of peak")
+    if with_oracle:
+        rec, ref = cpu_baseline(prob)
+        out["oracle"] = rec
+        for prec in ("fp64", "mixed"):
+            out[prec]["eps_vs_oracle"] = rel_inf(outs[prec].t().cpu().numpy(), ref)
+            log(f"[bench] C2 {prec}: eps vs oracle (all targets) {out[prec]['eps_vs_oracle']:.2e}")
+    return out, prob, tens
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the large-N and serving legs")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline workload (no C2, per-patch delta, upsampling, serving)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-memory-stream", action="store_true",
                     help="skip the memory-admitted stream leg")
+    ap.add_argument("--c5-full", action="store_true",
+                    help="run the memory-admitted stream at its stated size (64 capsules of "
+                         "N = 1,572,864 and 2,000 small ones, one pass; several minutes)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one device copy of this many bytes (PMC calibration)")
     args = ap.parse_args()
@@ -477,21 +609,27 @@ def main():
 
     dev = torch.device("cuda", 0)
     ctx = P.Context(0)
-    prob = W.c2()
+    rho64 = P.sl_get_param(ctx.ptr, P.SL_PARAM_RHO64)
+    prob = W.c3()
     tens = resident(dev, prob.surface.X, prob.surface.w, prob.f)
     pairs = prob.N * prob.N
-    log(f"[bench] workload c2: RBC 6x64x64, N={prob.N}, delta={prob.delta:.6g}")
+    log(f"[bench] workload rbc_6x256x256_sh8: N={prob.N}, delta={prob.delta:.6g}")
+    t0 = time.perf_counter()
     near = count_near(tens[0], prob.delta, [RHO_EXACT64, 5.0])
+    log(f"[bench] exact near-pair counts in {time.perf_counter() - t0:.1f} s: "
+        f"r < 6.9 delta {near[RHO_EXACT64]}, r < 5 delta {near[5.0]}")
 
     res = {}
     outs = {}
     for prec in ("fp64", "mixed"):
-        ms, kern_ms, outs[prec] = measure_precision(ctx, P, prob, tens, prec, args.steps, args.warmup)
+        ms, kern_ms, launches, med, outs[prec] = measure_headline(ctx, P, prob, tens, prec,
+                                                                  args.steps, args.warmup)
         near_p = near[RHO_EXACT64] if prec == "fp64" else near[5.0]
         res[prec] = {"ms_per_step": round(ms, 4), "gpair_s": round(pairs / (ms * 1e-3) / 1e9, 3),
-                     "roofline": roofline(prec, pairs, near_p, kern_ms)}
-        log(f"[bench] {prec}: {ms:.3f} ms/step  {res[prec]['gpair_s']:.1f} Gpair/s  "
-            f"pair kernel {kern_ms:.3f} ms  {res[prec]['roofline']['frac'] * 100:.1f}% of peak")
+                     "median_ms_30_reps": round(med, 4), "timed_pair_launches": launches,
+                     "roofline": roofline(prec, pairs, near_p, kern_ms, "rbc_6x256x256_sh8")}
+        log(f"[bench] C3 {prec}: {ms:.3f} ms/step (median {med:.3f})  {res[prec]['gpair_s']:.1f} "
+            f"Gpair/s  pair kernel {kern_ms:.3f} ms  {res[prec]['roofline']['frac'] * 100:.1f}% of peak")
 
     head = res[args.precision]
     other = "fp64" if args.precision == "mixed" else "mixed"
@@ -502,49 +640,43 @@ def main():
         "scaling": "strong", "vs_baseline": None,
         "dtype": "f32+f64" if args.precision == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": "rbc_6x64x64_sh8", "N": prob.N, "delta": prob.delta, "mu": 1.0,
-                   "precision": args.precision, "seed": W.SEED_C2,
+        "config": {"workload": "rbc_6x256x256_sh8", "N": prob.N, "delta": prob.delta, "mu": 1.0,
+                   "precision": args.precision, "rho64": rho64, "seed": W.SEED_C3,
                    "step": "sl_eval: sort + pack + pair kernel + reduction, all N targets"},
         "roofline": {k: head["roofline"][k] for k in
                      ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_detail": head["roofline"],
+        "median_ms_30_reps": head["median_ms_30_reps"],
         other: res[other],
     }
 
     if not args.no_cpu_baseline:
-        log("[bench] cpu baseline: oracle on the host")
-        line["cpu_baseline"], ref = cpu_baseline(prob)
+        log("[bench] cpu baseline: oracle on the host (4,096 sampled targets; 512 on one core)")
+        idx = W.c3_subset(prob.N, 4096)
+        line["cpu_baseline"], ref = cpu_baseline_sampled(prob, idx, idx[:512])
+        log(f"[bench] oracle: {line['cpu_baseline']['value']:.3f} Gpair/s on "
+            f"{line['cpu_baseline']['cores']} threads, {line['cpu_baseline']['one_core']['value']:.4f} "
+            f"on one ({line['cpu_baseline']['cpu_model']})")
         for prec in ("fp64", "mixed"):
-            e = rel_inf(outs[prec].t().cpu().numpy(), ref)
-            (line if prec == args.precision else line[prec])["eps_vs_oracle"] = e
-            log(f"[bench] {prec}: eps vs oracle {e:.2e}")
+            e = rel_inf(outs[prec].t().cpu().numpy()[idx], ref)
+            (line if prec == args.precision else line[prec])["eps_vs_oracle_4096_targets"] = e
+            log(f"[bench] C3 {prec}: eps vs oracle (4,096 targets) {e:.2e}")
+    del outs
 
     if not args.no_extras:
-        import oracle
-        line["patch_delta"] = patch_delta_leg(P, ctx, prob, tens, log)
+        line["c2"], p2, t2 = secondary_c2(P, ctx, dev, 100, 5, not args.no_cpu_baseline)
+        line["patch_delta"] = patch_delta_leg(P, ctx, p2, t2, log)
         line["upsampled"] = upsample_leg(P, ctx, dev, log)
-        p3 = W.c3()
-        t3 = resident(dev, p3.surface.X, p3.surface.w, p3.f)
-        big = {"workload": "rbc_6x256x256_sh8", "N": p3.N}
-        idx = W.c3_subset(p3.N, 256)
-        ref3 = oracle.single_layer(p3.surface.X, p3.surface.w, p3.f, p3.delta,
-                                   targets=p3.surface.X[idx])
-        for prec in ("fp64", "mixed"):
-            ms, kern_ms, u3 = measure_precision(ctx, P, p3, t3, prec, 3, 1)
-            big[prec] = {"ms_per_step": round(ms, 3),
-                         "gpair_s": round(p3.N ** 2 / (ms * 1e-3) / 1e9, 2),
-                         "pair_kernels_ms": round(kern_ms, 3),
-                         "eps_vs_oracle_256_targets": rel_inf(u3.t().cpu().numpy()[idx], ref3)}
-            log(f"[bench] N={p3.N} {prec}: {ms:.2f} ms  {big[prec]['gpair_s']:.0f} Gpair/s  "
-                f"eps {big[prec]['eps_vs_oracle_256_targets']:.2e}")
-        line["large_n"] = big
-        del t3
+        del t2
         if not args.no_serving:
             line["serving"] = serving_leg(P, dev, log)
             line["p50_ms"] = line["serving"]["mixed"]["poisson_0.9"]["p50_ms"]
             line["p99_ms"] = line["serving"]["mixed"]["poisson_0.9"]["p99_ms"]
         if not args.no_memory_stream:
-            line["memory_stream"] = memory_leg(P, dev, log)
+            line["memory_stream_sample"] = memory_leg(P, dev, log)
+    if args.c5_full:
+        line["memory_stream_full"] = memory_leg(P, dev, log, n_large=64, n_small=2000, passes=1,
+                                                budgets=("full",))
 
     if args.copy_bytes:
         a = torch.empty(args.copy_bytes // 8, dtype=torch.float64, device=dev).fill_(1.0)

@@ -22,7 +22,8 @@
 //  * Coherence: staging and surfaces are reused arena memory written while the kernel runs, so
 //    the kernel reads them only with vector loads after an acquire (never through the scalar
 //    cache, which is only invalidated at kernel launch); each lane loads one source of a
-//    cluster and the wave broadcasts it lane by lane with readlane.
+//    cluster into the wave's own LDS area, and the source loop reads each record back at one
+//    address across the wave (an LDS broadcast), so the arithmetic takes it as a vector operand.
 //  * Each target's sum runs in a fixed order (clusters ascending, one accumulator set) whatever
 //    else is in flight, so a request's result is bit-identical alone and in any mix.
 #include <math.h>
@@ -386,9 +387,12 @@ __device__ void run_pair(const ServeArgs &a, const WorkItem &it, const float4 *t
     const bool mixed = dfield(&dd->mixed) != 0;
     const TBlockRec *tbr = dfield(&dd->tbr);
     v.rec = tbr[it.a];
-    v.gap_far = mixed ? v.rec.gap_far_mixed : v.rec.gap_far;
+    const double rho64 = dfield(&dd->rho64);
+    // the mixed far cut of the surface (5 delta, widened for the box size) and this request's own
+    // double-precision zone
+    v.gap_far = mixed ? fmax(v.rec.gap_far_mixed, rho64 * delta) : v.rec.gap_far;
     v.dc = make_delta(delta);
-    v.dc32 = make_delta32(delta, dfield(&dd->rho64));
+    v.dc32 = make_delta32(delta, rho64);
     const int64_t t0 = (int64_t)it.a * kServeBlock;
     // One instance per path, so that no path holds another's registers; the mixed path with the
     // double-precision zone, whose pairs hold the most state, takes half of the targets at a time.
@@ -437,7 +441,7 @@ __global__ __launch_bounds__(kServeWaves * kWave) void k_serve(ServeArgs a)
     }
     int rounds = 0;
     for (;;) {
-        uint64_t idx = 0, got = 0, quit = 0;
+        uint64_t idx = 0, got = 0, quit = 0, w0 = 0, w1 = 0;
         if (lane == 0) {
             uint64_t h = __hip_atomic_load(&a.dc->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             uint64_t t = __hip_atomic_load(&a.dc->tail_mirror, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -458,10 +462,19 @@ __global__ __launch_bounds__(kServeWaves * kWave) void k_serve(ServeArgs a)
                 }
             }
             if (h < t) {
+                // Read the slot before claiming it.  Claims succeed in index order, so once the
+                // claim of h succeeds every item below h + 1 has been read, and any claim count
+                // published afterwards is a lower bound of the items read: the host never reuses
+                // a slot that a wave has claimed but not yet read.  (If the claim fails, the
+                // values are dropped.)
+                const WorkItem *slot = a.ring + (h & (kRingCap - 1));
+                const uint64_t v0 = ld_sys(slot), v1 = ld_sys((const uint64_t *)slot + 1);
                 if (__hip_atomic_compare_exchange_strong(&a.dc->head, &h, h + 1, __ATOMIC_ACQ_REL,
                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                     got = 1;
                     idx = h;
+                    w0 = v0;
+                    w1 = v1;
                 }
             } else {
                 const uint64_t stop = __hip_atomic_load(&a.dc->stop_mirror, __ATOMIC_RELAXED,
@@ -484,12 +497,12 @@ __global__ __launch_bounds__(kServeWaves * kWave) void k_serve(ServeArgs a)
         if (lane == 0) {
             __hip_atomic_fetch_max(&a.dc->last_activity, (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
-            // lower bound of the claim count for the host's ring-space check (plain store:
-            // out-of-order writers can only make it smaller, which is safe)
+            // claim count for the host's ring-space check: every item below it has been read
+            // (plain store: out-of-order writers can only make it smaller, which is safe)
             __hip_atomic_store(&a.ctl->claimed, idx + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
-        const WorkItem *slot = a.ring + (idx & (kRingCap - 1));
-        const uint64_t w0 = uni64(ld_sys(slot)), w1 = uni64(ld_sys((const uint64_t *)slot + 1));
+        w0 = uni64(w0);
+        w1 = uni64(w1);
         WorkItem it;
         it.slot = (uint32_t)w0;
         it.kind = (uint32_t)(w0 >> 32);
@@ -529,13 +542,13 @@ __global__ __launch_bounds__(256) void k_gather_surface(
     if ((threadIdx.x % kWave) == 0) osphere[p / kCluster] = make_double4(cx, cy, cz, rad);
 }
 
-// Target-block records for pair items, with the far thresholds of both precisions.
+// Target-block records for pair items, with the far thresholds of both precisions (the mixed one
+// without any double-precision zone: a request widens it by its own rho64).
 __global__ __launch_bounds__(kWave) void k_tblock_serve(const double *__restrict__ x,
                                                         const double *__restrict__ y,
                                                         const double *__restrict__ z,
                                                         const double *__restrict__ bbox,
-                                                        double delta, double rho64,
-                                                        TBlockRec *__restrict__ out)
+                                                        double delta, TBlockRec *__restrict__ out)
 {
     const int tb = blockIdx.x, lane = threadIdx.x;
     double px[kServeR], py[kServeR], pz[kServeR];
@@ -564,7 +577,7 @@ __global__ __launch_bounds__(kWave) void k_tblock_serve(const double *__restrict
         rec.cx = cx; rec.cy = cy; rec.cz = cz;
         rec.rad = sqrt(rr) * (1.0 + 0x1p-40);
         rec.gap_far = kRhoExact64 * delta;
-        rec.gap_far_mixed = fmax(fmax(kRhoExact32, rho64) * delta,
+        rec.gap_far_mixed = fmax(kRhoExact32 * delta,
                                  0x1p-10 * sqrt(fma(bx, bx, fma(by, by, __dmul_rn(bz, bz)))));
         rec.pad0 = rec.pad1 = 0.0;
         out[tb] = rec;
@@ -1069,7 +1082,7 @@ sl_status sl_surface_register(sl_ctx *ctx, int64_t n, const double *x, const dou
                            n, x, y, z, w, ps.centre, sf.x, sf.y, sf.z, sf.w, sf.x32, sf.y32, sf.z32,
                            sf.perm, sf.sphere);
         hipLaunchKernelGGL(k_tblock_serve, dim3((unsigned)(np / kServeBlock)), dim3(kWave), 0, s->aux,
-                           sf.x, sf.y, sf.z, ps.bbox, delta, ctx->rho64, sf.tbr);
+                           sf.x, sf.y, sf.z, ps.bbox, delta, sf.tbr);
         e = hipGetLastError();
     }
     if (scratch) (void)hipFreeAsync(scratch, s->aux);

@@ -61,6 +61,29 @@ def test_requests_match_oracle(ctx, surfaces, refs, precision, rho64):
     assert st.requests_done == len(rids) and st.kernel_launches >= 1
 
 
+def test_rho64_changed_after_registration(ctx, surfaces, refs):
+    """A request takes rho64 when it is submitted, also for a surface registered before: with
+    rho64 = 12 (every near pair within the double-precision zone, beyond the single-precision
+    cut of 5 delta) set after registration, the result equals that of a surface registered with
+    rho64 = 12 already set, bit for bit, and is closer to the oracle than with rho64 = 0."""
+    s, f, d = surfaces[2]
+    ref = refs[2]
+    h0 = ctx.register_surface(dev_t(s.X), dev_t(s.w), d)
+    rid, _ = ctx.submit(h0, dev_t(f), mu=0.8, precision="mixed")
+    u_zero = ctx.wait(rid, 60.0).cpu().numpy()
+    try:
+        ctx.set_rho64(12.0)
+        rid, _ = ctx.submit(h0, dev_t(f), mu=0.8, precision="mixed")
+        u_late = ctx.wait(rid, 60.0).cpu().numpy()
+        h1 = ctx.register_surface(dev_t(s.X), dev_t(s.w), d)
+        rid, _ = ctx.submit(h1, dev_t(f), mu=0.8, precision="mixed")
+        u_early = ctx.wait(rid, 60.0).cpu().numpy()
+    finally:
+        ctx.set_rho64(0.0)
+    assert np.array_equal(u_late, u_early)
+    assert eps(u_late, ref) < eps(u_zero, ref) and eps(u_late, ref) < TOL["mixed"]
+
+
 def test_alone_equals_mixed_bitwise(ctx, surfaces):
     """The same request served alone and inside a burst of other requests gives identical bits."""
     s, f, d = surfaces[2]

@@ -63,6 +63,8 @@ def _load():
         lib.slref_kernel.restype = None
         lib.slref_patch_delta.argtypes = [i64, i64, P, P, P, d, P]
         lib.slref_patch_delta.restype = ctypes.c_int
+        lib.slref_stokeslet.argtypes = [i64, P, P, P, P, P, P, i64, P, P, P, P, P, P, ctypes.c_int]
+        lib.slref_stokeslet.restype = ctypes.c_int
         lib.slref_max_threads.argtypes = []
         lib.slref_max_threads.restype = ctypes.c_int
         _lib = lib
@@ -105,6 +107,23 @@ def single_layer(X, w, f, delta, mu=1.0, targets=None, delta_tgt=None, nthreads=
     if rc != 0:
         raise ValueError("slref_eval rejected its arguments")
     return np.stack([ux, uy, uz], axis=1)
+
+
+def stokeslet(Y, g, targets, nthreads=0):
+    """Plain Stokeslet sum v (n_tgt, 3) = sum_j [g_j / r + (g_j . d) d / r^3], d = t - y_j, from
+    sources Y (N, 3) with densities g (N, 3) (no weights, no 1/(8 pi mu); r = 0 pairs skipped)."""
+    lib = _load()
+    Y = np.asarray(Y, dtype=np.float64).reshape(-1, 3)
+    g = np.asarray(g, dtype=np.float64).reshape(-1, 3)
+    T = np.asarray(targets, dtype=np.float64).reshape(-1, 3)
+    cols = [_col(Y[:, 0]), _col(Y[:, 1]), _col(Y[:, 2]), _col(g[:, 0]), _col(g[:, 1]),
+            _col(g[:, 2]), _col(T[:, 0]), _col(T[:, 1]), _col(T[:, 2])]
+    out = [np.zeros(T.shape[0]) for _ in range(3)]
+    rc = lib.slref_stokeslet(Y.shape[0], *[_ptr(c) for c in cols[:6]], T.shape[0],
+                             *[_ptr(c) for c in cols[6:]], *[_ptr(o) for o in out], int(nthreads))
+    if rc != 0:
+        raise ValueError("slref_stokeslet rejected its arguments")
+    return np.stack(out, axis=1)
 
 
 def patch_delta(X, n, C=1.0):

@@ -165,3 +165,44 @@ int slref_patch_delta(int64_t n_patches, int64_t n, const double *x, const doubl
     }
     return 0;
 }
+
+/*
+ * Plain (unregularized) Stokeslet sum, the kernel of the single-level FMM's far field
+ * (Sec. 5): the limit of the sum above where s1 = s2 = 1,
+ *
+ *   v(t_i) = sum_j [ g_j / r + (g_j . (t_i - y_j)) (t_i - y_j) / r^3 ],  r = |t_i - y_j| > 0,
+ *
+ * with the densities g_j given directly (no weights, no 1/(8 pi mu)).  A pair with r = 0 is
+ * skipped (the FMM never evaluates one).  Host pointers, structure-of-arrays; Neumaier sums,
+ * ascending j.  Returns 0, or -1 on invalid sizes.
+ */
+int slref_stokeslet(int64_t n_src, const double *sx, const double *sy, const double *sz,
+                    const double *gx, const double *gy, const double *gz, int64_t n_tgt,
+                    const double *tx, const double *ty, const double *tz, double *vx, double *vy,
+                    double *vz, int nthreads)
+{
+    if (n_src < 0 || n_tgt < 0) return -1;
+#ifdef _OPENMP
+    const int team = nthreads > 0 ? nthreads : omp_get_max_threads();
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 16) num_threads(team)
+    for (int64_t i = 0; i < n_tgt; ++i) {
+        neumaier ax = {0, 0}, ay = {0, 0}, az = {0, 0};
+        for (int64_t j = 0; j < n_src; ++j) {
+            const double dx = tx[i] - sx[j], dy = ty[i] - sy[j], dz = tz[i] - sz[j];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == 0.0) continue;
+            const double r = sqrt(r2);
+            const double gd = gx[j] * dx + gy[j] * dy + gz[j] * dz;
+            nm_add(&ax, gx[j] / r + gd * dx / (r2 * r));
+            nm_add(&ay, gy[j] / r + gd * dy / (r2 * r));
+            nm_add(&az, gz[j] / r + gd * dz / (r2 * r));
+        }
+        vx[i] = ax.s + ax.c;
+        vy[i] = ay.s + ay.c;
+        vz[i] = az.s + az.c;
+    }
+    return 0;
+}

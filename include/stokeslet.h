@@ -194,6 +194,45 @@ sl_status sl_eval_upsampled(sl_ctx *ctx, sl_precision prec, int64_t n_patches, i
                             double C, double mu, double *ux, double *uy, double *uz, void *stream);
 
 /*
+ * The single layer by the single-level kernel-independent FMM of Sec. 5 ("Fast multipole method
+ * based acceleration"), targets = sources, asynchronous on `stream` after a synchronization in the
+ * middle (see below):
+ *
+ *   1. k-means clustering of the n points into k clusters (the paper takes k = 100): Lloyd's
+ *      iteration from the points at indices floor(j n / k), nearest centroid by squared distance
+ *      (ties to the lower index), exact centroid sums of the coordinates quantized to 2^-24 of the
+ *      points' extent; it stops at the first assignment that changes no label or after max_iter
+ *      assignments;
+ *   2. per cluster, a cube of half width a (the box of its points' bounding box, half its largest
+ *      side) with equivalent sources on the lattice of p_edge points per edge on the boundary of
+ *      the cube of half width 1.05 a (N_eq = p^3 - (p - 2)^3 points), whose densities are fitted
+ *      (Tikhonov least squares, weight 1e-8) to the plain-Stokeslet potential of the cluster's own
+ *      points at the same lattice on the check cube of half width 2.95 a;
+ *   3. per target, the regularized sum over the points of near clusters and the plain Stokeslet
+ *      sum over the equivalent sources of far clusters: cluster S is far from cluster T when T's
+ *      box lies outside the cube of half width 3 a_S around S's centre and at least 6.9 delta_T
+ *      from S's box (delta_T the largest delta of T's points), where the smoothing factors equal 1.
+ *
+ *  x, y, z, w, fx, fy, fz:  the n points, weights and density (device arrays, as sl_eval).
+ *  delta, delta_tgt:         as sl_eval (one delta, or one per point).
+ *  k:                        clusters (1..min(n, 1024)); p_edge: 3..12; max_iter: 1..10000.
+ *  ux, uy, uz:               output at the points (n each).
+ *  labels_out:               NULL, or n int32: the cluster of each point.
+ *
+ * The result approximates sl_eval's; the error falls with p_edge (about 1e-4 relative at p = 4 to
+ * 1e-7 at p = 8 on the surfaces of the paper's shape family).  The call enqueues the clustering,
+ * then waits for it on `stream` (the cluster boxes come back to the host, which forms the near /
+ * far lists and the padded layout), then enqueues the rest; the unit box's fit operator is built
+ * on the host once per p_edge and kept by the context.  Deterministic.  SL_EINVAL for bad sizes,
+ * scalars, NULL or aliasing arrays; SL_ENOMEM / SL_EHIP on allocation or launch failures.
+ */
+sl_status sl_eval_fmm(sl_ctx *ctx, sl_precision prec, int64_t n, const double *x, const double *y,
+                      const double *z, const double *w, const double *fx, const double *fy,
+                      const double *fz, double delta, const double *delta_tgt, double mu, int k,
+                      int p_edge, int max_iter, double *ux, double *uy, double *uz, int32_t *labels_out,
+                      void *stream);
+
+/*
  * Serving: device-resident surfaces and continuous batching.
  *
  * sl_surface_register copies n nodes (x, y, z, w: device arrays) into library-owned HBM,

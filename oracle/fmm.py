@@ -84,8 +84,9 @@ def kmeans(X, k, max_iter=KMEANS_MAX_ITER):
         labels = new
         counts = np.bincount(labels, minlength=k)
         for c in range(3):
-            sums = np.zeros(k, dtype=np.int64)
-            np.add.at(sums, labels, Q[:, c])
+            # integer coordinates below 2^24, at most 2^28 points: every partial sum is an integer
+            # below 2^53, so the double-precision bincount is exact whatever its order
+            sums = np.bincount(labels, weights=Q[:, c], minlength=k).astype(np.int64)
             has = counts > 0
             C[has, c] = lo[c] + (sums[has].astype(np.float64) / counts[has].astype(np.float64)) / scale
     return labels, C, it
@@ -161,9 +162,11 @@ def unit_operator(p):
 
 
 def single_layer_fmm(X, w, f, delta, mu=1.0, delta_tgt=None, k=100, p=6, max_iter=KMEANS_MAX_ITER,
-                     nthreads=0, details=False):
+                     nthreads=0, details=False, only=None):
     """u (N, 3) at the nodes X by the single-level FMM (targets = sources).  With details=True also
-    returns a dict with the labels, boxes, neighbour mask and the near and far parts."""
+    returns a dict with the labels, boxes, neighbour mask and the near and far parts.  `only`: an
+    iterable of cluster indices whose targets are evaluated (the others are NaN) -- the clustering
+    and every cluster's equivalent sources are computed in full either way."""
     import oracle
     X = np.asarray(X, dtype=np.float64)
     f = np.asarray(f, dtype=np.float64)
@@ -194,9 +197,12 @@ def single_layer_fmm(X, w, f, delta, mu=1.0, delta_tgt=None, k=100, p=6, max_ite
     scale = 1.0 / (8.0 * math.pi * mu)
     u_near = np.zeros((N, 3))
     u_far = np.zeros((N, 3))
-    for T in range(k):
+    if only is not None:
+        u_near[:] = np.nan
+    for T in (range(k) if only is None else only):
         if cnt[T] == 0:
             continue
+        u_far[members[T]] = 0.0
         tg = members[T]
         nb = [S for S in range(k) if cnt[S] and near[T, S]]
         fr = [S for S in range(k) if cnt[S] and not near[T, S]]

@@ -11,7 +11,7 @@ from . import _binding
 from ._binding import (EXPORTED, SL_EBUSY, SL_EHIP, SL_EINVAL, SL_ENOMEM, SL_ENOTFOUND, SL_ETIMEDOUT,
                        SL_FP64, SL_MIXED, SL_OK, SL_PARAM_KERNEL_TIMING, SL_PARAM_RHO64,
                        SL_PARAM_TARGETS_PER_LANE, SL_PARAM_WAVES_PER_SIMD, SlError, check, load, sl_create,
-                       sl_destroy, sl_eval, sl_eval_noalloc, sl_eval_upsampled, sl_get_param, sl_get_stats, sl_last_error,
+                       sl_destroy, sl_eval, sl_eval_fmm, sl_eval_noalloc, sl_eval_upsampled, sl_get_param, sl_get_stats, sl_last_error,
                        sl_patch_delta, sl_poll,
                        sl_request_bytes, sl_set_param, sl_submit, sl_surface_register,
                        sl_surface_release, sl_wait)
@@ -144,6 +144,32 @@ class Context:
                                    int(st_obj.cuda_stream))
         check(st, "sl_eval_upsampled")
         return U.t()
+
+    def single_layer_fmm(self, X, w, f, delta, mu=1.0, delta_tgt=None, k=100, p_edge=6,
+                         max_iter=100, precision="fp64", stream=None, out=None, labels=False):
+        """u (N, 3) at the nodes X (targets = sources) by the single-level FMM: k clusters,
+        p_edge equivalent points per cube edge.  With labels=True also returns the cluster of
+        each node (int32 device tensor).  Synchronizes `stream` once (after the clustering)."""
+        import torch
+        cur = torch.cuda.current_stream()
+        st_obj = cur if stream is None else stream
+        if st_obj != cur:
+            st_obj.wait_stream(cur)
+        with torch.cuda.stream(st_obj):
+            Xs, fs = _soa(X), _soa(f)
+            ws = w.to(torch.float64).contiguous()
+            n = Xs.shape[1]
+            dts = None if delta_tgt is None else delta_tgt.to(torch.float64).contiguous()
+            U = out if out is not None else torch.empty((3, n), dtype=torch.float64, device=Xs.device)
+            L = torch.empty(n, dtype=torch.int32, device=Xs.device) if labels else None
+            st = sl_eval_fmm(self.ptr, PRECISIONS[precision], n, Xs[0].data_ptr(), Xs[1].data_ptr(),
+                             Xs[2].data_ptr(), ws.data_ptr(), fs[0].data_ptr(), fs[1].data_ptr(),
+                             fs[2].data_ptr(), float(delta), None if dts is None else dts.data_ptr(),
+                             float(mu), int(k), int(p_edge), int(max_iter), U[0].data_ptr(),
+                             U[1].data_ptr(), U[2].data_ptr(), None if L is None else L.data_ptr(),
+                             int(st_obj.cuda_stream))
+        check(st, "sl_eval_fmm")
+        return (U.t(), L) if labels else U.t()
 
     # -- serving ---------------------------------------------------------------------------
     def register_surface(self, X, w, delta) -> int:

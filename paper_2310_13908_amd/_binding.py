@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "SL_OK", -1: "SL_EINVAL", -2: "SL_ENOMEM", -3: "SL_EBUSY", -4
 
 # Every symbol include/stokeslet.h declares.
 EXPORTED = ["sl_create", "sl_destroy", "sl_last_error", "sl_set_param", "sl_get_param", "sl_eval",
-            "sl_eval_noalloc", "sl_patch_delta", "sl_eval_upsampled",
+            "sl_eval_noalloc", "sl_eval_fmm", "sl_patch_delta", "sl_eval_upsampled",
             "sl_surface_register", "sl_surface_release", "sl_submit", "sl_poll", "sl_wait",
             "sl_request_bytes", "sl_get_stats"]
 
@@ -65,6 +65,7 @@ def load():
         "sl_get_param": ([P, i32, ctypes.POINTER(d)], i32),
         "sl_eval": ([P, i32, i64, V, V, V, V, V, V, V, i64, V, V, V, d, V, d, V, V, V, V], i32),
         "sl_eval_noalloc": ([P, i32, i64, V, V, V, V, V, V, V, i64, V, V, V, d, V, d, V, V, V, V], i32),
+        "sl_eval_fmm": ([P, i32, i64, V, V, V, V, V, V, V, d, V, d, i32, i32, i32, V, V, V, V, V], i32),
         "sl_patch_delta": ([P, i64, i64, V, V, V, d, V, V], i32),
         "sl_eval_upsampled": ([P, i32, i64, i64, i32, V, V, V, V, V, V, V, V, d, d, V, V, V, V], i32),
         "sl_surface_register": ([P, i64, V, V, V, V, d, ctypes.POINTER(u64)], i32),
@@ -127,6 +128,12 @@ def sl_eval_noalloc(ctx, prec, n_src, sx, sy, sz, w, fx, fy, fz, n_tgt, tx, ty, 
                     delta_tgt, mu, ux, uy, uz, stream) -> int:
     return load().sl_eval_noalloc(ctx, prec, n_src, sx, sy, sz, w, fx, fy, fz, n_tgt, tx, ty, tz,
                                   delta, delta_tgt, mu, ux, uy, uz, stream)
+
+
+def sl_eval_fmm(ctx, prec, n, x, y, z, w, fx, fy, fz, delta, delta_tgt, mu, k, p_edge, max_iter,
+                ux, uy, uz, labels_out, stream) -> int:
+    return load().sl_eval_fmm(ctx, prec, n, x, y, z, w, fx, fy, fz, delta, delta_tgt, mu, k, p_edge,
+                              max_iter, ux, uy, uz, labels_out, stream)
 
 
 def sl_patch_delta(ctx, n_patches, n, x, y, z, C, delta_out, stream) -> int:

@@ -72,6 +72,16 @@ struct PairArgs {
     void *tblock_scratch;    // tblock_scratch_bytes(n_tblocks): per-target-block spheres
     int records_ready;       // 1: the source gather already wrote the target records (and
                              // zeroed the work counter), so launch_pair skips k_tblock
+    // Single-level FMM (sl_fmm.hip): points grouped by cluster box, each box padded to whole
+    // target groups and source clusters.  fmm_mode 0: every source cluster (the plain sum);
+    // 1: only clusters of boxes near the target group's box; 2: only clusters of far boxes,
+    // every pair plain (the far field from equivalent sources); 3: only clusters of the target
+    // group's own box, every pair plain (check potentials).
+    int fmm_mode = 0;
+    int fmm_k = 0;                       // number of boxes
+    const int32_t *fmm_box_src = nullptr;   // box of each source cluster of 64
+    const int32_t *fmm_box_tgt = nullptr;   // box of each block of 64 targets
+    const uint8_t *fmm_near = nullptr;      // [k][k]: box T near box S
 };
 
 // Optional events recorded around the pair kernel.
@@ -211,4 +221,6 @@ struct sl_ctx {
     double pair_ms = 0.0;
     // spline matrices of the upsampling step, per (n, factor): device memory, freed by sl_destroy
     std::unordered_map<int64_t, double *> splines;
+    // unit-box operators of the single-level FMM, per points per cube edge: device memory
+    std::unordered_map<int, double *> fmm_ops;
 };

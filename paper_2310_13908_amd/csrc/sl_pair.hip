@@ -273,7 +273,7 @@ __device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec &re
                                           const TBlockRec &own, bool grouped, const Src &S,
                                           const double4 *__restrict__ sphere, const float4 *tab,
                                           double *zs, float4 *stg, double *__restrict__ part, int tb,
-                                          int k)
+                                          int k, int box)
 {
     const uint32_t K = (uint32_t)a.n_ways;
     const int lane = threadIdx.x % kWave;
@@ -313,8 +313,13 @@ __device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec &re
     uint32_t rank_far = 0, rank_near = 0;
     for (int64_t c0 = 0; c0 < n_cl; c0 += kWave) {
         const int64_t cl = c0 + lane;
-        const bool valid = cl < n_cl;
-        const bool far = valid && cluster_is_far(rec, sphere[valid ? cl : 0]);
+        bool valid = cl < n_cl;
+        if (a.fmm_mode) {   // the FMM's box lists (wave-uniform mode)
+            const int bs = a.fmm_box_src[valid ? cl : 0];
+            const bool nb = a.fmm_near[(int64_t)box * a.fmm_k + bs] != 0;
+            valid = valid && (a.fmm_mode == 1 ? nb : (a.fmm_mode == 2 ? !nb : bs == box));
+        }
+        const bool far = valid && (a.fmm_mode >= 2 || cluster_is_far(rec, sphere[valid ? cl : 0]));
         const bool near = valid && !far;
         const uint64_t mf = __builtin_amdgcn_ballot_w64(far);
         const uint64_t mn = __builtin_amdgcn_ballot_w64(near);
@@ -404,11 +409,12 @@ __global__ __launch_bounds__(G * kWave) void k_pair(PairArgs a, const TBlockRec 
         if (item >= n_items) break;
         const int g = (int)(item / K);
         const int tb = g * G + w;
+        const int box = a.fmm_mode ? a.fmm_box_tgt[(int64_t)g * G * R] : 0;
         if (tb < a.n_tblocks)
             pair_item<R, VARD, MIXED, ZONE, STAGE>(
                 a, recs[g], recs[G > 1 ? n_groups + tb : g], G > 1, S, sphere, sh_tab,
                 sh_zone + (MIXED && ZONE ? w * R * 6 * kWave : 0),
-                sh_stage + (STAGE ? w * 2 * kCluster : 0), part, tb, (int)(item % K));
+                sh_stage + (STAGE ? w * 2 * kCluster : 0), part, tb, (int)(item % K), box);
     }
 }
 

@@ -1002,9 +1002,10 @@ void sl_destroy(sl_ctx *ctx)
     for (auto &ev : ctx->timed)
         for (hipEvent_t e : {ev.e0, ev.e1}) (void)hipEventDestroy(e);
     for (auto ev : ctx->spare_events) (void)hipEventDestroy(ev);
-    if (!ctx->splines.empty()) {
+    if (!ctx->splines.empty() || !ctx->fmm_ops.empty()) {
         (void)hipSetDevice(ctx->device);
         for (auto &kv : ctx->splines) (void)hipFree(kv.second);
+        for (auto &kv : ctx->fmm_ops) (void)hipFree(kv.second);
     }
     delete ctx;
 }

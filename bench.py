@@ -271,6 +271,44 @@ def upsample_leg(P, ctx, dev, log, steps=3, warmup=1):
     return res
 
 
+def fmm_leg(P, ctx, dev, log, steps=3, warmup=1):
+    """The single-level FMM of Sec. 5 against the direct sum on the shape of the paper's FMM table
+    (the a = 0.6 ellipsoid, reduced volume 0.9) at the upsampled sizes of its rows (m = 32, 64, 96:
+    N_up = 6 (4 (m - 1))^2 = 92,256, 381,024 and 866,400 points), delta* per patch, SH density,
+    k = 100 clusters and p = 5, 6, 8 points per cube edge (N_eq = 98, 152, 296 against the table's
+    96, 128, 256).  A step is one evaluation: sl_eval (direct) or sl_eval_fmm (clustering, fit,
+    near and far fields); eps_FMM is against the direct sum on the same GPU, in FP64."""
+    import torch
+    from capsule_inputs import ELLIPSOID_PAPER, make_surface, sh_force
+    out = {"workload": "ellipsoid 0.6:1:1 at N_up of the paper's FMM table, delta* per patch, "
+                       "SH density, k = 100", "rows": []}
+    for m, p in ((32, 5), (64, 6), (96, 8)):
+        n = 4 * (m - 1)
+        t0 = time.perf_counter()
+        s = make_surface(ELLIPSOID_PAPER, n)
+        f = sh_force(s.x0, 9000 + m)
+        X, w, F = resident(dev, s.X, s.w, f)
+        D = ctx.patch_delta(X, n)
+        torch.cuda.synchronize()
+        row = {"m": m, "N_up": s.N, "p_edge": p, "N_eq": p ** 3 - (p - 2) ** 3}
+        U = torch.empty((3, s.N), dtype=torch.float64, device=dev)
+        V = torch.empty((3, s.N), dtype=torch.float64, device=dev)
+        for prec in ("fp64", "mixed"):
+            td = time_steps(lambda: ctx.single_layer(X, w, F, 0.0, delta_tgt=D, precision=prec, out=U),
+                            steps, warmup)
+            tf = time_steps(lambda: ctx.single_layer_fmm(X, w, F, 0.0, delta_tgt=D, k=100, p_edge=p,
+                                                         precision=prec, out=V), steps, warmup)
+            row[prec] = {"direct_ms": round(td * 1e3, 2), "fmm_ms": round(tf * 1e3, 2),
+                         "speedup": round(td / tf, 3),
+                         "eps_fmm_vs_direct": rel_inf(V.t().cpu().numpy(), U.t().cpu().numpy())}
+            log(f"[bench] FMM m={m} N_up={s.N} p={p} {prec}: direct {td * 1e3:.1f} ms, FMM {tf * 1e3:.1f} ms "
+                f"(x{td / tf:.2f}), eps_FMM {row[prec]['eps_fmm_vs_direct']:.1e}  "
+                f"({time.perf_counter() - t0:.0f} s)")
+        out["rows"].append(row)
+        del X, w, F, D, U, V
+    return out
+
+
 def roofline(precision, pairs, near, kern_ms, workload):
     """Vector-ALU roofline of the pair kernel: algorithmic flops per launch (28 per far pair, 49
     per pair within the smoothing radius, exact counts) over its average launch duration, against
@@ -668,6 +706,7 @@ def main():
         line["patch_delta"] = patch_delta_leg(P, ctx, p2, t2, log)
         line["upsampled"] = upsample_leg(P, ctx, dev, log)
         del t2
+        line["fmm"] = fmm_leg(P, ctx, dev, log)
         if not args.no_serving:
             line["serving"] = serving_leg(P, dev, log)
             line["p50_ms"] = line["serving"]["mixed"]["poisson_0.9"]["p50_ms"]

@@ -686,6 +686,7 @@ sl_status sl_eval_fmm(sl_ctx *ctx, sl_precision prec, int64_t n, const double *x
         wps = ctx->waves_per_simd;
     }
     if (R == 0) R = mixed ? 1 : (np <= ((int64_t)1 << 17) ? 1 : 2);
+    R = R > 2 ? 2 : R;   // the pair kernel's cluster-list instances keep at most two targets a lane
     const int waves_wanted = ctx->n_cu * 4 * wps;
     PairPlan pn = plan_pairs(np, np, R, waves_wanted, mixed);                     // near field
     PairPlan pf = plan_pairs((int64_t)k * pe, np, R, waves_wanted, mixed);       // far field

@@ -268,7 +268,7 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
 // ballots, and this way's clusters are processed in ascending cluster order.  Every wave of a
 // group walks the same clusters, so the group's waves share each source record in the scalar
 // cache.
-template <int R, bool VARD, bool MIXED, bool ZONE, bool STAGE>
+template <int R, bool VARD, bool MIXED, bool ZONE, bool STAGE, bool BOX>
 __device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec &rec,
                                           const TBlockRec &own, bool grouped, const Src &S,
                                           const double4 *__restrict__ sphere, const float4 *tab,
@@ -314,12 +314,12 @@ __device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec &re
     for (int64_t c0 = 0; c0 < n_cl; c0 += kWave) {
         const int64_t cl = c0 + lane;
         bool valid = cl < n_cl;
-        if (a.fmm_mode) {   // the FMM's box lists (wave-uniform mode)
+        if constexpr (BOX) {   // the FMM's box lists (wave-uniform mode)
             const int bs = a.fmm_box_src[valid ? cl : 0];
             const bool nb = a.fmm_near[(int64_t)box * a.fmm_k + bs] != 0;
             valid = valid && (a.fmm_mode == 1 ? nb : (a.fmm_mode == 2 ? !nb : bs == box));
         }
-        const bool far = valid && (a.fmm_mode >= 2 || cluster_is_far(rec, sphere[valid ? cl : 0]));
+        const bool far = valid && ((BOX && a.fmm_mode >= 2) || cluster_is_far(rec, sphere[valid ? cl : 0]));
         const bool near = valid && !far;
         const uint64_t mf = __builtin_amdgcn_ballot_w64(far);
         const uint64_t mn = __builtin_amdgcn_ballot_w64(near);
@@ -377,7 +377,7 @@ __device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec &re
 // counter; wave w of the workgroup takes target block G * group + w.  Items are group-major, so
 // the K ways of a group run at about the same time.  ZONE (mixed path only): some near pairs are
 // summed in double precision (rho64 > 0); without it the zone's code and LDS state are left out.
-template <int R, bool VARD, bool MIXED, bool ZONE, int G>
+template <int R, bool VARD, bool MIXED, bool ZONE, int G, bool BOX>
 __global__ __launch_bounds__(G * kWave) void k_pair(PairArgs a, const TBlockRec *__restrict__ recs,
                                                     const double *__restrict__ Sd,
                                                     const float *__restrict__ Sf,
@@ -409,9 +409,9 @@ __global__ __launch_bounds__(G * kWave) void k_pair(PairArgs a, const TBlockRec 
         if (item >= n_items) break;
         const int g = (int)(item / K);
         const int tb = g * G + w;
-        const int box = a.fmm_mode ? a.fmm_box_tgt[(int64_t)g * G * R] : 0;
+        const int box = BOX ? a.fmm_box_tgt[(int64_t)g * G * R] : 0;
         if (tb < a.n_tblocks)
-            pair_item<R, VARD, MIXED, ZONE, STAGE>(
+            pair_item<R, VARD, MIXED, ZONE, STAGE, BOX>(
                 a, recs[g], recs[G > 1 ? n_groups + tb : g], G > 1, S, sphere, sh_tab,
                 sh_zone + (MIXED && ZONE ? w * R * 6 * kWave : 0),
                 sh_stage + (STAGE ? w * 2 * kCluster : 0), part, tb, (int)(item % K), box);
@@ -485,7 +485,7 @@ template <int R>
 hipError_t launch_r(const PairArgs &a, const PairPlan &p, bool mixed, bool vard, hipStream_t st,
                     const PairTiming *tm)
 {
-    static int occ[6] = {0, 0, 0, 0, 0, 0};
+    static int occ[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int G = mixed ? group_size<true>() : group_size<false>();
     const int n_groups = (p.n_tblocks + G - 1) / G;
     TBlockRec *rec = reinterpret_cast<TBlockRec *>(a.tblock_scratch);
@@ -504,19 +504,35 @@ hipError_t launch_r(const PairArgs &a, const PairPlan &p, bool mixed, bool vard,
     if (tm && tm->e0) (void)hipEventRecord(tm->e0, st);
     const int64_t n_items = (int64_t)n_groups * p.n_ways;
     const bool zone = mixed && a.rho64 > 0.0;
-#define SL_PAIR_LAUNCH(V, M, Z, SLOT)                                                               \
-    hipLaunchKernelGGL((k_pair<R, V, M, Z, group_size<M>()>),                                        \
-                       dim3(work_grid(k_pair<R, V, M, Z, group_size<M>()>, group_size<M>() * kWave,   \
+#define SL_PAIR_LAUNCH(V, M, Z, B, SLOT)                                                            \
+    hipLaunchKernelGGL((k_pair<R, V, M, Z, group_size<M>(), B>),                                     \
+                       dim3(work_grid(k_pair<R, V, M, Z, group_size<M>(), B>, group_size<M>() * kWave,\
                                       occ[SLOT], p.n_cu, n_items)),                                  \
                        dim3(group_size<M>() * kWave), 0, st, a, rec, s.d, s.f32, s.sphere, a.part, ctr)
-    if (vard) {
-        if (zone) SL_PAIR_LAUNCH(true, true, true, 3);
-        else if (mixed) SL_PAIR_LAUNCH(true, true, false, 5);
-        else SL_PAIR_LAUNCH(true, false, false, 1);
+    if (a.fmm_mode) {
+        // The FMM's cluster lists: instances of their own, so that the plain sum's kernels carry
+        // none of the list code (two targets per lane at most).
+        if constexpr (R <= 2) {
+            if (vard) {
+                if (zone) SL_PAIR_LAUNCH(true, true, true, true, 9);
+                else if (mixed) SL_PAIR_LAUNCH(true, true, false, true, 11);
+                else SL_PAIR_LAUNCH(true, false, false, true, 7);
+            } else {
+                if (zone) SL_PAIR_LAUNCH(false, true, true, true, 8);
+                else if (mixed) SL_PAIR_LAUNCH(false, true, false, true, 10);
+                else SL_PAIR_LAUNCH(false, false, false, true, 6);
+            }
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else if (vard) {
+        if (zone) SL_PAIR_LAUNCH(true, true, true, false, 3);
+        else if (mixed) SL_PAIR_LAUNCH(true, true, false, false, 5);
+        else SL_PAIR_LAUNCH(true, false, false, false, 1);
     } else {
-        if (zone) SL_PAIR_LAUNCH(false, true, true, 2);
-        else if (mixed) SL_PAIR_LAUNCH(false, true, false, 4);
-        else SL_PAIR_LAUNCH(false, false, false, 0);
+        if (zone) SL_PAIR_LAUNCH(false, true, true, false, 2);
+        else if (mixed) SL_PAIR_LAUNCH(false, true, false, false, 4);
+        else SL_PAIR_LAUNCH(false, false, false, false, 0);
     }
 #undef SL_PAIR_LAUNCH
     if (tm && tm->e1) (void)hipEventRecord(tm->e1, st);

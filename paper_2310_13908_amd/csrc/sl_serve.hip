@@ -45,7 +45,10 @@ constexpr int kMaxSlots = 1024;                  // admitted requests in flight
 constexpr uint64_t kRingCap = 1ull << 21;        // work items in the ring (power of two)
 constexpr int kServeWavesPerSimd = 4;
 constexpr int kServeWaves = 4;                     // waves per workgroup (one smoothing table)
-constexpr double kIdleSeconds = 0.25;            // persistent kernel exits after this idle time
+// The persistent kernel exits after this idle time.  While it runs it holds every wave slot, so
+// other work on the device (sl_eval, registrations) waits for it: short, while a relaunch costs
+// only a launch.
+constexpr double kIdleSeconds = 0.02;
 constexpr double kGatherWaitSeconds = 2.0;       // bound on a pair item's wait for its gathers
 constexpr double kPollSeconds = 2e-6;            // spacing of the waves' host-memory polls
 
@@ -349,7 +352,7 @@ __device__ void run_pair(const ServeArgs &a, const WorkItem &it, const float4 *t
     for (int rounds = 1;; rounds = rounds < 8 ? rounds * 2 : 8) {
         uint64_t g = 0;
         if (lane == 0)
-            g = __hip_atomic_load(&a.dc->gathers_done[it.slot], __ATOMIC_ACQUIRE,
+            g = __hip_atomic_load(&a.dc->gathers_done[it.slot], __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
         if (uni64(g) >= gather_target) {
             ready = true;
@@ -444,7 +447,7 @@ __global__ __launch_bounds__(kServeWaves * kWave) void k_serve(ServeArgs a)
         uint64_t idx = 0, got = 0, quit = 0, w0 = 0, w1 = 0;
         if (lane == 0) {
             uint64_t h = __hip_atomic_load(&a.dc->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            uint64_t t = __hip_atomic_load(&a.dc->tail_mirror, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            uint64_t t = __hip_atomic_load(&a.dc->tail_mirror, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (h >= t) {
                 // At most one wave every ~2 us reads the host's tail and stop flag (PCIe) and
                 // mirrors them into device memory for the others.
@@ -453,10 +456,10 @@ __global__ __launch_bounds__(kServeWaves * kWave) void k_serve(ServeArgs a)
                 if (now > lp + a.poll_ticks &&
                     __hip_atomic_compare_exchange_strong(&a.dc->last_poll, &lp, now, __ATOMIC_RELAXED,
                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    t = __hip_atomic_load(&a.ctl->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
-                    const uint64_t stop = __hip_atomic_load(&a.ctl->stop, __ATOMIC_ACQUIRE,
+                    t = __hip_atomic_load(&a.ctl->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    const uint64_t stop = __hip_atomic_load(&a.ctl->stop, __ATOMIC_RELAXED,
                                                             __HIP_MEMORY_SCOPE_SYSTEM);
-                    __hip_atomic_fetch_max(&a.dc->tail_mirror, t, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_max(&a.dc->tail_mirror, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if (stop)
                         __hip_atomic_store(&a.dc->stop_mirror, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
@@ -469,7 +472,11 @@ __global__ __launch_bounds__(kServeWaves * kWave) void k_serve(ServeArgs a)
                 // values are dropped.)
                 const WorkItem *slot = a.ring + (h & (kRingCap - 1));
                 const uint64_t v0 = ld_sys(slot), v1 = ld_sys((const uint64_t *)slot + 1);
-                if (__hip_atomic_compare_exchange_strong(&a.dc->head, &h, h + 1, __ATOMIC_ACQ_REL,
+                // the slot's loads complete before the claim (a wave-local wait, no cache
+                // maintenance: idle waves poll here, and an agent-scope fence per poll would
+                // write back and invalidate L2 under the waves that are working)
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                if (__hip_atomic_compare_exchange_strong(&a.dc->head, &h, h + 1, __ATOMIC_RELAXED,
                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                     got = 1;
                     idx = h;

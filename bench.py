@@ -365,8 +365,13 @@ def run_stream(ctx, P, handles, fs, us, pairs, arrivals, precision, spin):
     t0 = time.perf_counter()
     k = 0
     outstanding = []
+    next_note = 20.0
     while k < n or outstanding:
         now = time.perf_counter() - t0
+        if now > next_note:
+            log(f"[bench] stream: {k} submitted, {n - k + len(outstanding) - (n - k)} outstanding "
+                f"after {now:.0f} s")
+            next_note += 20.0
         while k < n and arrivals[k] <= now:
             rid = ctx.submit_prepared(handles[k], fs[k], us[k], precision=precision)
             rid_of[rid] = k

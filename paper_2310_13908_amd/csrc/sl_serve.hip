@@ -87,10 +87,13 @@ struct DevCounters {                      // device memory
     uint64_t head;                        // items claimed
     uint64_t last_activity;               // wall clock of the latest claim
     uint64_t tail_mirror;                 // latest host tail seen by any wave
-    uint64_t stop_mirror;                 // host stop flag seen by any wave
+    uint64_t stop_mirror;                 // launch id of a wave that saw the host's stop flag
     uint64_t last_poll;                   // wall clock of the latest read of host memory
-    uint64_t launch_seen;                 // id of the launch that last reset last_activity
-    uint64_t pad[2];
+    uint64_t exit_launch;                 // id of a launch whose waves are to exit once the
+                                          // queue is empty (set by the first wave to see the
+                                          // stop flag or the idle limit)
+    uint64_t running;                     // items claimed and not yet finished
+    uint64_t pad[1];
     uint64_t gathers_done[kMaxSlots];     // monotonic per slot
     uint64_t items_done[kMaxSlots];       // monotonic per slot
 };
@@ -353,7 +356,7 @@ __device__ void run_pair(const ServeArgs &a, const WorkItem &it, const float4 *t
         uint64_t g = 0;
         if (lane == 0)
             g = __hip_atomic_load(&a.dc->gathers_done[it.slot], __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
+                                  __HIP_MEMORY_SCOPE_SYSTEM);
         if (uni64(g) >= gather_target) {
             ready = true;
             break;
@@ -429,42 +432,44 @@ __global__ __launch_bounds__(kServeWaves * kWave) void k_serve(ServeArgs a)
     // From here on every wave works on its own: it pulls its own items and leaves on its own.
     const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
     const Stage stage{sh_d[wv], sh_f[wv]};
-    if (lane == 0) {
-        // The first wave of this launch starts the idle clock; later-starting waves must not
-        // push it forward, or the kernel would outlive its idle limit.
-        uint64_t seen = __hip_atomic_load(&a.dc->launch_seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // It also clears the stop mirror left by a drain of the previous launch.
-        if (seen != a.launch_id &&
-            __hip_atomic_compare_exchange_strong(&a.dc->launch_seen, &seen, a.launch_id, __ATOMIC_RELAXED,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-            __hip_atomic_store(&a.dc->stop_mirror, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_max(&a.dc->last_activity, (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
+    // The idle clock of this wave starts no earlier than the wave itself: the shared activity
+    // time may still hold the previous launch's last claim, and a wave that read it would take
+    // the new launch for idle.  The stop and exit marks carry the launch id for the same reason.
+    const uint64_t t_start = uni64(wall_clock64());
     int rounds = 0;
     for (;;) {
         uint64_t idx = 0, got = 0, quit = 0, w0 = 0, w1 = 0;
         if (lane == 0) {
-            uint64_t h = __hip_atomic_load(&a.dc->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            uint64_t t = __hip_atomic_load(&a.dc->tail_mirror, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (h >= t) {
+            // Polling loads at system scope: coherent across the XCDs' L2 caches without any
+            // cache maintenance (agent-scope relaxed loads may hit a stale line in this XCD's L2,
+            // and agent-scope acquires would invalidate the whole L2).
+            uint64_t h = __hip_atomic_load(&a.dc->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            uint64_t t = __hip_atomic_load(&a.dc->tail_mirror, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            // Once this launch is exiting, no wave takes new work: items published meanwhile
+            // wait for the relaunch.  (A few waves left claiming would keep the launch alive on
+            // a fraction of the chip while requests keep coming.)
+            const bool exiting = __hip_atomic_load(&a.dc->exit_launch, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_SYSTEM) == a.launch_id;
+            if (exiting) {
+                quit = 1;
+            } else if (h >= t) {
                 // At most one wave every ~2 us reads the host's tail and stop flag (PCIe) and
                 // mirrors them into device memory for the others.
                 const uint64_t now = wall_clock64();
-                uint64_t lp = __hip_atomic_load(&a.dc->last_poll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                uint64_t lp = __hip_atomic_load(&a.dc->last_poll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 if (now > lp + a.poll_ticks &&
                     __hip_atomic_compare_exchange_strong(&a.dc->last_poll, &lp, now, __ATOMIC_RELAXED,
-                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
                     t = __hip_atomic_load(&a.ctl->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                     const uint64_t stop = __hip_atomic_load(&a.ctl->stop, __ATOMIC_RELAXED,
                                                             __HIP_MEMORY_SCOPE_SYSTEM);
-                    __hip_atomic_fetch_max(&a.dc->tail_mirror, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_max(&a.dc->tail_mirror, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                     if (stop)
-                        __hip_atomic_store(&a.dc->stop_mirror, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&a.dc->stop_mirror, a.launch_id, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_SYSTEM);
                 }
             }
-            if (h < t) {
+            if (!exiting && h < t) {
                 // Read the slot before claiming it.  Claims succeed in index order, so once the
                 // claim of h succeeds every item below h + 1 has been read, and any claim count
                 // published afterwards is a lower bound of the items read: the host never reuses
@@ -477,19 +482,29 @@ __global__ __launch_bounds__(kServeWaves * kWave) void k_serve(ServeArgs a)
                 // write back and invalidate L2 under the waves that are working)
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 if (__hip_atomic_compare_exchange_strong(&a.dc->head, &h, h + 1, __ATOMIC_RELAXED,
-                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
                     got = 1;
                     idx = h;
                     w0 = v0;
                     w1 = v1;
+                    __hip_atomic_fetch_add(&a.dc->running, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 }
-            } else {
-                const uint64_t stop = __hip_atomic_load(&a.dc->stop_mirror, __ATOMIC_RELAXED,
-                                                        __HIP_MEMORY_SCOPE_AGENT);
-                const uint64_t last = __hip_atomic_load(&a.dc->last_activity, __ATOMIC_RELAXED,
-                                                        __HIP_MEMORY_SCOPE_AGENT);
+            } else if (!exiting) {
+                const bool stop = __hip_atomic_load(&a.dc->stop_mirror, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_SYSTEM) == a.launch_id;
+                uint64_t last = __hip_atomic_load(&a.dc->last_activity, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_SYSTEM);
+                last = last > t_start ? last : t_start;
                 const uint64_t now = wall_clock64();
-                if (stop || (now > last && now - last > a.idle_ticks)) quit = 1;
+                const uint64_t running = __hip_atomic_load(&a.dc->running, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_SYSTEM);
+                // All waves of a launch exit together, on the host's stop flag once the queue is
+                // empty, or when nothing has been claimed for the idle limit and nothing runs.
+                if (stop || (running == 0 && now > last && now - last > a.idle_ticks)) {
+                    __hip_atomic_store(&a.dc->exit_launch, a.launch_id, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_SYSTEM);
+                    quit = 1;
+                }
             }
         }
         got = uni64(got);
@@ -503,7 +518,7 @@ __global__ __launch_bounds__(kServeWaves * kWave) void k_serve(ServeArgs a)
         idx = uni64(idx);
         if (lane == 0) {
             __hip_atomic_fetch_max(&a.dc->last_activity, (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
             // claim count for the host's ring-space check: every item below it has been read
             // (plain store: out-of-order writers can only make it smaller, which is safe)
             __hip_atomic_store(&a.ctl->claimed, idx + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -520,6 +535,8 @@ __global__ __launch_bounds__(kServeWaves * kWave) void k_serve(ServeArgs a)
             run_gather(a, it);
         else
             run_pair(a, it, sh_tab, stage);
+        if (lane == 0)
+            __hip_atomic_fetch_add(&a.dc->running, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 

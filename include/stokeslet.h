@@ -58,11 +58,14 @@ typedef struct sl_ctx sl_ctx;   /* opaque; one per device */
 /* Create a context on HIP device `device`.  `hbm_budget_bytes` bounds the device memory
  * held by resident surfaces and in-flight serving requests (0 = 90% of the free memory at
  * creation).  One-shot sl_eval calls allocate their workspace stream-ordered and are not
- * counted against the budget.  Returns SL_EINVAL for a bad device or NULL `out`. */
+ * counted against the budget; they take it from a memory pool of the context, which keeps what
+ * it has allocated (at most the largest workspaces in use at once) until sl_destroy, so that
+ * repeated calls allocate nothing new.  Returns SL_EINVAL for a bad device or NULL `out`. */
 sl_status sl_create(int device, size_t hbm_budget_bytes, sl_ctx **out);
 
-/* Drain the serving queue, stop its persistent kernel and free everything the context owns.
- * NULL is a no-op. */
+/* Drain the serving queue, stop its persistent kernel and free everything the context owns
+ * (it first waits for all work on the device, which may still use pool workspaces).  NULL is a
+ * no-op. */
 void sl_destroy(sl_ctx *ctx);
 
 /* Message describing the last failure on the calling thread ("" if none).  The pointer is

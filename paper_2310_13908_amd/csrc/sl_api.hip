@@ -185,7 +185,7 @@ sl_status eval_common(const char *who, sl_ctx *ctx, sl_precision prec, int64_t n
             bytes = carve(nullptr, ws, n_sort, np_s, np_t, !same, mixed, vard, plan.n_ways);
         }
     } else {
-        hipError_t ea = hipMallocAsync((void **)&base, bytes, st);
+        hipError_t ea = ws_alloc(ctx, (void **)&base, bytes, st);
         if (ea != hipSuccess) return hip_fail(ea, (w_ + "workspace").c_str());
     }
     carve(base, ws, n_sort, np_s, np_t, !same, mixed, vard, plan.n_ways);
@@ -301,7 +301,22 @@ sl_status sl_create(int device, size_t hbm_budget_bytes, sl_ctx **out)
         return fail(SL_EINVAL, std::string("sl_create: built for gfx950, device is ") + prop.gcnArchName);
     size_t free_b = 0, total_b = 0;
     SL_HIP(hipMemGetInfo(&free_b, &total_b));
+    hipMemPoolProps props;
+    memset(&props, 0, sizeof(props));
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = device;
+    hipMemPool_t pool = nullptr;
+    SL_HIP(hipMemPoolCreate(&pool, &props));
+    uint64_t keep = UINT64_MAX;
+    const hipError_t ep = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    if (ep != hipSuccess) {
+        (void)hipMemPoolDestroy(pool);
+        return hip_fail(ep, "sl_create: hipMemPoolSetAttribute");
+    }
     sl_ctx *c = new sl_ctx();
+    c->pool = pool;
     c->device = device;
     c->n_cu = prop.multiProcessorCount;
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);

@@ -561,7 +561,7 @@ sl_status sl_eval_fmm(sl_ctx *ctx, sl_precision prec, int64_t n, const double *x
     const size_t o_dmax = take((size_t)k * 8), o_cnt = take((size_t)k * 4), o_rank = take((size_t)n * 4);
     const size_t o_wcnt = take((size_t)n_waves * k * 4);
     char *A = nullptr;
-    hipError_t e = hipMallocAsync((void **)&A, off, st);
+    hipError_t e = ws_alloc(ctx, (void **)&A, off, st);
     if (e != hipSuccess) return hip_fail(e, "sl_eval_fmm: workspace");
     KmState *kst = (KmState *)(A + o_state);
     double *gbox = (double *)(A + o_box), *C = (double *)(A + o_C);
@@ -709,7 +709,7 @@ sl_status sl_eval_fmm(sl_ctx *ctx, sl_precision prec, int64_t n, const double *x
     const size_t b_part = take((size_t)(pn.n_ways + pf.n_ways) * 3 * np * 8);
     const size_t b_cpart = take((size_t)pk.n_ways * 3 * npc * 8);
     const size_t b_tbs = take(tblock_scratch_bytes((int)(std::max(np, npc) / kWave)));
-    e = hipMallocAsync((void **)&B, off, st);
+    e = ws_alloc(ctx, (void **)&B, off, st);
     if (e != hipSuccess) return cleanup(e, "sl_eval_fmm: workspace");
     auto at = [&](size_t o) { return B + o; };
     SortedOut so;

@@ -223,4 +223,16 @@ struct sl_ctx {
     std::unordered_map<int64_t, double *> splines;
     // unit-box operators of the single-level FMM, per points per cube edge: device memory
     std::unordered_map<int, double *> fmm_ops;
+    // Stream-ordered workspaces come from this pool, which keeps what it has allocated until the
+    // context is destroyed: the device's default pool returns its memory at every synchronization,
+    // and a caller that synchronizes between calls would pay a fresh allocation each time.
+    hipMemPool_t pool = nullptr;
 };
+
+namespace sl {
+// Workspace of `bytes` from the context's pool, stream-ordered on `st` (freed with hipFreeAsync).
+inline hipError_t ws_alloc(sl_ctx *ctx, void **p, size_t bytes, hipStream_t st)
+{
+    return hipMallocFromPoolAsync(p, bytes, ctx->pool, st);
+}
+}

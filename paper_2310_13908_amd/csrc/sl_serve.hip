@@ -1031,6 +1031,12 @@ void sl_destroy(sl_ctx *ctx)
         for (auto &kv : ctx->splines) (void)hipFree(kv.second);
         for (auto &kv : ctx->fmm_ops) (void)hipFree(kv.second);
     }
+    if (ctx->pool) {
+        // workspaces are returned stream-ordered: let the work that uses them finish first
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+        (void)hipMemPoolDestroy(ctx->pool);
+    }
     delete ctx;
 }
 
@@ -1095,7 +1101,7 @@ sl_status sl_surface_register(sl_ctx *ctx, int64_t n, const double *x, const dou
 
     PackScratch ps;
     char *scratch = nullptr;
-    hipError_t e = hipMallocAsync((void **)&scratch, sort_scratch_bytes(n), s->aux);
+    hipError_t e = ws_alloc(ctx, (void **)&scratch, sort_scratch_bytes(n), s->aux);
     if (e == hipSuccess) {
         carve_sort_scratch(scratch, n, ps);
         e = launch_bbox(x, y, z, n, nullptr, nullptr, nullptr, 0, ps, s->aux);

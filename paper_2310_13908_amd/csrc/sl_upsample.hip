@@ -197,7 +197,7 @@ sl_status sl_eval_upsampled(sl_ctx *ctx, sl_precision prec, int64_t n_patches, i
     // workspace: 9 fine fields (x, y, z, W, f (3), w, delta) and u (3); scratch T
     const int64_t scratch = n_patches * nf * nf;     // >= n_patches * n * nf and n_patches * nf * n
     void *base = nullptr;
-    hipError_t e = hipMallocAsync(&base, (size_t)(12 * Nf + scratch) * sizeof(double), st);
+    hipError_t e = ws_alloc(ctx, &base, (size_t)(12 * Nf + scratch) * sizeof(double), st);
     if (e != hipSuccess) return hip_fail(e, "sl_eval_upsampled: workspace");
     double *Ws = static_cast<double *>(base);
     double *X[3] = {Ws, Ws + Nf, Ws + 2 * Nf}, *Wu = Ws + 3 * Nf;

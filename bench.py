@@ -635,6 +635,9 @@ def main():
     ap.add_argument("--c5-full", action="store_true",
                     help="run the memory-admitted stream at its stated size (64 capsules of "
                          "N = 1,572,864 and 2,000 small ones, one pass; several minutes)")
+    ap.add_argument("--workload", choices=["c3", "c2"], default="c3",
+                    help="workload of the timed step: RBC 6x256x256 (the headline) or RBC 6x64x64 "
+                         "(for counter runs of the smaller case)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one device copy of this many bytes (PMC calibration)")
     args = ap.parse_args()
@@ -653,10 +656,11 @@ def main():
     dev = torch.device("cuda", 0)
     ctx = P.Context(0)
     rho64 = P.sl_get_param(ctx.ptr, P.SL_PARAM_RHO64)
-    prob = W.c3()
+    wl, tag, prob, seed = (("rbc_6x256x256_sh8", "C3", W.c3(), W.SEED_C3) if args.workload == "c3"
+                           else ("rbc_6x64x64_sh8", "C2", W.c2(), W.SEED_C2))
     tens = resident(dev, prob.surface.X, prob.surface.w, prob.f)
     pairs = prob.N * prob.N
-    log(f"[bench] workload rbc_6x256x256_sh8: N={prob.N}, delta={prob.delta:.6g}")
+    log(f"[bench] workload {wl}: N={prob.N}, delta={prob.delta:.6g}")
     t0 = time.perf_counter()
     near = count_near(tens[0], prob.delta, [RHO_EXACT64, 5.0])
     log(f"[bench] exact near-pair counts in {time.perf_counter() - t0:.1f} s: "
@@ -670,8 +674,8 @@ def main():
         near_p = near[RHO_EXACT64] if prec == "fp64" else near[5.0]
         res[prec] = {"ms_per_step": round(ms, 4), "gpair_s": round(pairs / (ms * 1e-3) / 1e9, 3),
                      "median_ms_30_reps": round(med, 4), "timed_pair_launches": launches,
-                     "roofline": roofline(prec, pairs, near_p, kern_ms, "rbc_6x256x256_sh8")}
-        log(f"[bench] C3 {prec}: {ms:.3f} ms/step (median {med:.3f})  {res[prec]['gpair_s']:.1f} "
+                     "roofline": roofline(prec, pairs, near_p, kern_ms, wl)}
+        log(f"[bench] {tag} {prec}: {ms:.3f} ms/step (median {med:.3f})  {res[prec]['gpair_s']:.1f} "
             f"Gpair/s  pair kernel {kern_ms:.3f} ms  {res[prec]['roofline']['frac'] * 100:.1f}% of peak")
 
     head = res[args.precision]
@@ -683,8 +687,8 @@ def main():
         "scaling": "strong", "vs_baseline": None,
         "dtype": "f32+f64" if args.precision == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": "rbc_6x256x256_sh8", "N": prob.N, "delta": prob.delta, "mu": 1.0,
-                   "precision": args.precision, "rho64": rho64, "seed": W.SEED_C3,
+        "config": {"workload": wl, "N": prob.N, "delta": prob.delta, "mu": 1.0,
+                   "precision": args.precision, "rho64": rho64, "seed": seed,
                    "step": "sl_eval: sort + pack + pair kernel + reduction, all N targets"},
         "roofline": {k: head["roofline"][k] for k in
                      ("bound", "achieved", "peak", "unit", "frac", "traffic")},
@@ -703,7 +707,7 @@ def main():
         for prec in ("fp64", "mixed"):
             e = rel_inf(outs[prec].t().cpu().numpy()[idx], ref)
             (line if prec == args.precision else line[prec])["eps_vs_oracle_4096_targets"] = e
-            log(f"[bench] C3 {prec}: eps vs oracle (4,096 targets) {e:.2e}")
+            log(f"[bench] {tag} {prec}: eps vs oracle (4,096 targets) {e:.2e}")
     del outs
 
     if not args.no_extras:

@@ -30,7 +30,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "slref.c")
-LIB_PATH = os.path.join(_HERE, "libslref.so")
+# SLREF_LIB names another build of slref.c to load (the sanitizer test uses it).
+LIB_PATH = os.environ.get("SLREF_LIB") or os.path.join(_HERE, "libslref.so")
 
 _lib = None
 

@@ -16,9 +16,11 @@
 //  * One persistent kernel serves all requests: each wavefront claims the next item with a CAS
 //    on a device counter, runs it and counts it done; the wave finishing a request's last item
 //    publishes the request's sequence number to host memory with a system-scope release.
-//    Every wave exits once the ring is drained and either the host asked it to stop or no item
-//    was claimed for kIdleSeconds; the host relaunches it when new work arrives.  The only
-//    other wait (a pair item waiting for its request's gathers) is bounded as well.
+//    The waves of a launch exit together, once the ring is drained and either the host asked
+//    them to stop or no item was claimed for kIdleSeconds while none was running (the first wave
+//    to see this marks the launch as exiting, and no wave claims after that mark); the host
+//    relaunches the kernel when new work arrives.  The only other wait (a pair item waiting for
+//    its request's gathers) is bounded as well.
 //  * Coherence: staging and surfaces are reused arena memory written while the kernel runs, so
 //    the kernel reads them only with vector loads after an acquire (never through the scalar
 //    cache, which is only invalidated at kernel launch); each lane loads one source of a

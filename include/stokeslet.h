@@ -68,9 +68,10 @@ sl_status sl_create(int device, size_t hbm_budget_bytes, sl_ctx **out);
  * no-op. */
 void sl_destroy(sl_ctx *ctx);
 
-/* Message describing the last failure on the calling thread ("" if none).  The pointer is
- * valid until the next library call on that thread. */
-const char *sl_last_error(void);
+/* Message describing the last failure on the calling thread ("" if none), whatever the
+ * context; `ctx` may be NULL (failures of sl_create have none).  The pointer is valid until
+ * the next library call on that thread. */
+const char *sl_last_error(const sl_ctx *ctx);
 
 /* Tunables.
  * SL_PARAM_RHO64: in SL_MIXED, pairs with r/delta below this value are summed in double

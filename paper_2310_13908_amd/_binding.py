@@ -60,7 +60,7 @@ def load():
     sig = {
         "sl_create": ([i32, ctypes.c_size_t, ctypes.POINTER(P)], i32),
         "sl_destroy": ([P], None),
-        "sl_last_error": ([], ctypes.c_char_p),
+        "sl_last_error": ([P], ctypes.c_char_p),
         "sl_set_param": ([P, i32, d], i32),
         "sl_get_param": ([P, i32, ctypes.POINTER(d)], i32),
         "sl_eval": ([P, i32, i64, V, V, V, V, V, V, V, i64, V, V, V, d, V, d, V, V, V, V], i32),
@@ -86,7 +86,7 @@ def load():
 
 def check(status: int, what: str = ""):
     if status != SL_OK:
-        msg = load().sl_last_error().decode(errors="replace")
+        msg = load().sl_last_error(None).decode(errors="replace")
         raise SlError(status, f"{what}: {msg}" if what else msg)
     return status
 
@@ -104,8 +104,8 @@ def sl_destroy(ctx) -> None:
     load().sl_destroy(ctx)
 
 
-def sl_last_error() -> str:
-    return load().sl_last_error().decode(errors="replace")
+def sl_last_error(ctx=None) -> str:
+    return load().sl_last_error(ctx).decode(errors="replace")
 
 
 def sl_set_param(ctx, key: int, value: float) -> int:

@@ -283,7 +283,11 @@ using namespace sl;
 
 extern "C" {
 
-const char *sl_last_error(void) { return g_last_error.c_str(); }
+const char *sl_last_error(const sl_ctx *ctx)
+{
+    (void)ctx;   // the message is kept per thread, whatever the context
+    return g_last_error.c_str();
+}
 
 sl_status sl_create(int device, size_t hbm_budget_bytes, sl_ctx **out)
 {

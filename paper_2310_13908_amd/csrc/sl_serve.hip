@@ -53,6 +53,11 @@ constexpr int kServeWaves = 4;                     // waves per workgroup (one s
 constexpr double kIdleSeconds = 0.02;
 constexpr double kGatherWaitSeconds = 2.0;       // bound on a pair item's wait for its gathers
 constexpr double kPollSeconds = 2e-6;            // spacing of the waves' host-memory polls
+// Pair items of large requests are split over source ranges: one piece per kPieceClusters source
+// clusters, at most kMaxPieces.  Each piece keeps its partial sums (24 B per target) in the
+// request's staging, and the last piece of a target block to finish adds them in piece order.
+constexpr int64_t kPieceClusters = 768;
+constexpr int64_t kMaxPieces = 4;
 
 enum : uint32_t { kItemGather = 0, kItemPair = 1 };
 
@@ -76,6 +81,9 @@ struct ReqDesc {
     uint64_t gather_target, items_target, seq;
     int64_t mixed;
     double rho64;                         // mixed: double-precision zone p < rho64
+    int64_t pieces;                       // pieces per target block (1: not split)
+    double *part;                         // pieces > 1: [pieces][3][np] partial sums (staging)
+    uint32_t *bdone;                      // pieces > 1: [np / 128] pieces done per target block
 };
 
 struct ServeCtl {                         // host-pinned
@@ -178,6 +186,11 @@ __device__ void run_gather(const ServeArgs &a, const WorkItem &it)
         gx[p] = vx; gy[p] = vy; gz[p] = vz;
         if (mixed) { gx32[p] = (float)vx; gy32[p] = (float)vy; gz32[p] = (float)vz; }
     }
+    if (field(&d->pieces) > 1) {   // the split pair items' counters of the blocks starting here
+        uint32_t *bdone = field(&d->bdone);
+        for (int64_t k = (int64_t)it.a / kServeBlock + threadIdx.x % kWave; k < (int64_t)it.b / kServeBlock; k += kWave)
+            bdone[k] = 0u;
+    }
     __threadfence();
     if (threadIdx.x % kWave == 0)
         __hip_atomic_fetch_add(&a.dc->gathers_done[it.slot], 1ull, __ATOMIC_RELEASE,
@@ -202,14 +215,16 @@ struct BlockView {
     const double4 *sphere;
     double *ux, *uy, *uz;
     int64_t np;
+    int64_t c_lo, c_hi;                   // the source clusters of this item
+    double *part;                         // split items: this piece's partial sums, else nullptr
     double scale, gap_far;
     TBlockRec rec;
     DeltaC dc;
     DeltaC32 dc32;
 };
 
-// The sums of the R * 64 targets from t0 on over every source cluster of the request, written
-// to the caller's arrays.  MIXED: single precision with the per-cluster two-sum, and with ZONE
+// The sums of the R * 64 targets from t0 on over the source clusters [c_lo, c_hi) of the request,
+// written to the caller's arrays (or, for a piece of a split item, unscaled to its partial sums).  MIXED: single precision with the per-cluster two-sum, and with ZONE
 // the pairs below rho64 in double precision; otherwise every pair in double precision.
 template <bool MIXED, bool ZONE, int R>
 __device__ __forceinline__ void serve_targets(const BlockView &v, int64_t t0, const float4 *tab,
@@ -235,8 +250,7 @@ __device__ __forceinline__ void serve_targets(const BlockView &v, int64_t t0, co
         }
     }
 
-    const int64_t n_cl = v.np / kCluster;
-    for (int64_t c = 0; c < n_cl; ++c) {
+    for (int64_t c = v.c_lo; c < v.c_hi; ++c) {
         const int64_t j0 = c * kCluster;
         const bool far = uni64(cluster_is_far(v.rec, v.sphere[c], v.gap_far) ? 1u : 0u) != 0;
         // stage what this cluster's loop reads
@@ -321,7 +335,7 @@ __device__ __forceinline__ void serve_targets(const BlockView &v, int64_t t0, co
     for (int r = 0; r < R; ++r) {
         const int64_t i = t0 + r * kWave + lane;
         const int32_t idx = v.perm[i];
-        if (idx >= 0) {
+        if (idx >= 0 || v.part) {
             double ox, oy, oz;
             if constexpr (MIXED) {
                 ox = (double)hx[r] + (double)lx[r];
@@ -337,10 +351,38 @@ __device__ __forceinline__ void serve_targets(const BlockView &v, int64_t t0, co
                 oy = ay[r];
                 oz = az[r];
             }
-            v.ux[idx] = ox * v.scale;
-            v.uy[idx] = oy * v.scale;
-            v.uz[idx] = oz * v.scale;
+            if (v.part) {
+                v.part[i] = ox;
+                v.part[v.np + i] = oy;
+                v.part[2 * v.np + i] = oz;
+            } else {
+                v.ux[idx] = ox * v.scale;
+                v.uy[idx] = oy * v.scale;
+                v.uz[idx] = oz * v.scale;
+            }
         }
+    }
+}
+
+// The last piece of a split target block: the pieces' partial sums added in piece order,
+// scaled and scattered to the caller's arrays.
+__device__ void combine_pieces(const BlockView &v, const double *part, int64_t pieces, int64_t t0)
+{
+    const int lane = threadIdx.x % kWave;
+    for (int r = 0; r < kServeR; ++r) {
+        const int64_t i = t0 + r * kWave + lane;
+        const int32_t idx = v.perm[i];
+        if (idx < 0) continue;
+        double ox = 0.0, oy = 0.0, oz = 0.0;
+        for (int64_t q = 0; q < pieces; ++q) {
+            const double *pq = part + q * 3 * v.np;
+            ox += pq[i];
+            oy += pq[v.np + i];
+            oz += pq[2 * v.np + i];
+        }
+        v.ux[idx] = ox * v.scale;
+        v.uy[idx] = oy * v.scale;
+        v.uz[idx] = oz * v.scale;
     }
 }
 
@@ -402,6 +444,12 @@ __device__ void run_pair(const ServeArgs &a, const WorkItem &it, const float4 *t
     v.dc = make_delta(delta);
     v.dc32 = make_delta32(delta, rho64);
     const int64_t t0 = (int64_t)it.a * kServeBlock;
+    const int64_t pieces = dfield(&dd->pieces);
+    double *const part = pieces > 1 ? dfield(&dd->part) : nullptr;
+    const int64_t n_cl = v.np / kCluster;
+    v.c_lo = (int64_t)it.b * n_cl / pieces;
+    v.c_hi = ((int64_t)it.b + 1) * n_cl / pieces;
+    v.part = part ? part + (int64_t)it.b * 3 * v.np : nullptr;
     // One instance per path, so that no path holds another's registers; the mixed path with the
     // double-precision zone, whose pairs hold the most state, takes half of the targets at a time.
     if (!mixed) {
@@ -412,6 +460,20 @@ __device__ void run_pair(const ServeArgs &a, const WorkItem &it, const float4 *t
         serve_targets<true, false, kServeR>(v, t0, tab, st);
     }
     __threadfence();
+    if (part) {
+        // Each piece releases its partial sums before counting itself done on the block; the
+        // last one acquires them all, adds them in piece order and writes the block's output
+        // (released by the fence below, before the item is counted done on the request).
+        uint32_t old = 0;
+        if (lane == 0)
+            old = __hip_atomic_fetch_add(dfield(&dd->bdone) + it.a, 1u, __ATOMIC_ACQ_REL,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+        if (uni64(old) + 1 == (uint64_t)pieces) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            combine_pieces(v, part, pieces, t0);
+            __threadfence();
+        }
+    }
     if (lane == 0) {
         const uint64_t items_target = dfield(&dd->items_target);
         const uint64_t old = __hip_atomic_fetch_add(&a.dc->items_done[it.slot], 1ull,
@@ -758,9 +820,17 @@ size_t surface_bytes(int64_t np)
                     round_up(nb * (int64_t)sizeof(TBlockRec), 256));
 }
 
+int64_t pieces_for(int64_t np)
+{
+    const int64_t p = np / kCluster / kPieceClusters;
+    return p < 2 ? 1 : (p > kMaxPieces ? kMaxPieces : p);
+}
+
 size_t staging_bytes(int64_t np, bool mixed)
 {
-    return (size_t)(3 * round_up(np * 8, 256) + (mixed ? 3 * round_up(np * 4, 256) : 0));
+    const int64_t pieces = pieces_for(np);
+    return (size_t)(3 * round_up(np * 8, 256) + (mixed ? 3 * round_up(np * 4, 256) : 0) +
+                    (pieces > 1 ? round_up(pieces * 3 * np * 8, 256) + round_up(np / kServeBlock * 4, 256) : 0));
 }
 
 }  // namespace
@@ -856,7 +926,8 @@ void Server::admit_locked()
         HostReq &r = reqs[pending.front()];
         Surface &s = surfaces[r.surf];
         const uint64_t n_gather = (uint64_t)((s.np + kGatherChunk - 1) / kGatherChunk);
-        const uint64_t n_pair = (uint64_t)(s.np / kServeBlock);
+        const int64_t pieces = pieces_for(s.np);
+        const uint64_t n_pair = (uint64_t)(s.np / kServeBlock * pieces);
         const uint64_t claimed = __atomic_load_n(&ctl->claimed, __ATOMIC_ACQUIRE);
         if (free_slots.empty() || tail + n_gather + n_pair - claimed > kRingCap) break;
         char *st = arena.alloc(staging_bytes(s.np, r.mixed));
@@ -881,9 +952,16 @@ void Server::admit_locked()
         if (r.mixed) {
             d.gx32 = (float *)p; p += round_up(s.np * 4, 256);
             d.gy32 = (float *)p; p += round_up(s.np * 4, 256);
-            d.gz32 = (float *)p;
+            d.gz32 = (float *)p; p += round_up(s.np * 4, 256);
         } else {
             d.gx32 = d.gy32 = d.gz32 = nullptr;
+        }
+        d.pieces = pieces;
+        d.part = nullptr;
+        d.bdone = nullptr;
+        if (pieces > 1) {
+            d.part = (double *)p; p += round_up(pieces * 3 * s.np * 8, 256);
+            d.bdone = (uint32_t *)p;
         }
         d.n = s.n;
         d.np = s.np;
@@ -903,7 +981,8 @@ void Server::admit_locked()
             ring[(tail + k) & (kRingCap - 1)] = WorkItem{(uint32_t)slot, kItemGather, (uint32_t)a, (uint32_t)b};
         }
         for (uint64_t k = 0; k < n_pair; ++k)
-            ring[(tail + n_gather + k) & (kRingCap - 1)] = WorkItem{(uint32_t)slot, kItemPair, (uint32_t)k, 0u};
+            ring[(tail + n_gather + k) & (kRingCap - 1)] =
+                WorkItem{(uint32_t)slot, kItemPair, (uint32_t)(k / pieces), (uint32_t)(k % pieces)};
         tail += n_gather + n_pair;
         __atomic_store_n(&ctl->tail, tail, __ATOMIC_RELEASE);
         active.push_back(r.id);
@@ -960,7 +1039,7 @@ void Server::loop()
             const sl_status st = ensure_kernel_locked();
             if (st != SL_OK) {
                 fatal = st;
-                fatal_msg = sl_last_error();
+                fatal_msg = sl_last_error(ctx);
                 done_cv.notify_all();
             }
         }

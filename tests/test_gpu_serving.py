@@ -105,6 +105,42 @@ def test_alone_equals_mixed_bitwise(ctx, surfaces):
         assert np.array_equal(alone, mixed)
 
 
+@pytest.fixture(scope="module")
+def split_case():
+    """RBC n = 180 (N = 194,400, 3,040 source clusters): its pair items are split into three
+    pieces of uneven cluster ranges; the oracle on 384 sampled targets."""
+    import oracle
+    s = make_surface(RBC, 180)
+    f = sh_force(s.x0, 909)
+    d = 2 * math.pi / 181
+    idx = np.sort(np.random.default_rng(4).choice(s.N, 384, replace=False))
+    ref = oracle.single_layer(s.X, s.w, f, d, mu=0.8, targets=s.X[idx])
+    return s, f, d, idx, ref
+
+
+def test_split_request_matches_oracle_and_mix(ctx, surfaces, split_case):
+    """A request large enough for split pair items: parity with the oracle on sampled targets in
+    both precisions, and the same bits alone and inside a burst of small requests."""
+    s, f, d, idx, ref = split_case
+    h = ctx.register_surface(dev_t(s.X), dev_t(s.w), d)
+    others = [ctx.register_surface(dev_t(o.X), dev_t(o.w), od) for o, of, od in surfaces]
+    for precision in ("fp64", "mixed"):
+        rid, _ = ctx.submit(h, dev_t(f), mu=0.8, precision=precision)
+        alone = ctx.wait(rid, 60.0).cpu().numpy()
+        assert eps(alone[idx], ref) < TOL[precision]
+        burst = []
+        for k in range(8):
+            o, of, od = surfaces[k % len(surfaces)]
+            burst.append(ctx.submit(others[k % len(surfaces)], dev_t(of * (1 + k)), mu=0.8,
+                                    precision=("fp64", "mixed")[k % 2])[0])
+            if k == 3:
+                mid, _ = ctx.submit(h, dev_t(f), mu=0.8, precision=precision)
+        in_mix = ctx.wait(mid, 60.0).cpu().numpy()
+        for r in burst:
+            ctx.wait(r, 60.0)
+        assert np.array_equal(alone, in_mix)
+
+
 def test_admission_under_small_budget(surfaces, refs):
     """Budget that holds the surfaces but only a couple of requests' staging at a time:
     every request still completes, correctly, and the admitted bytes stay within the budget."""

@@ -54,10 +54,11 @@ constexpr double kIdleSeconds = 0.02;
 constexpr double kGatherWaitSeconds = 2.0;       // bound on a pair item's wait for its gathers
 constexpr double kPollSeconds = 2e-6;            // spacing of the waves' host-memory polls
 // Pair items of large requests are split over source ranges: one piece per kPieceClusters source
-// clusters, at most kMaxPieces.  Each piece keeps its partial sums (24 B per target) in the
-// request's staging, and the last piece of a target block to finish adds them in piece order.
-constexpr int64_t kPieceClusters = 768;
-constexpr int64_t kMaxPieces = 4;
+// clusters, at most kMaxPieces, so that no item holds a wave for long.  Each piece keeps its
+// partial sums (24 B per target) in the request's staging, and the last piece of a target block
+// to finish adds them in piece order.
+constexpr int64_t kPieceClusters = 384;
+constexpr int64_t kMaxPieces = 8;
 
 enum : uint32_t { kItemGather = 0, kItemPair = 1 };
 

@@ -107,7 +107,7 @@ def test_alone_equals_mixed_bitwise(ctx, surfaces):
 
 @pytest.fixture(scope="module")
 def split_case():
-    """RBC n = 180 (N = 194,400, 3,040 source clusters): its pair items are split into three
+    """RBC n = 180 (N = 194,400, 3,040 source clusters): its pair items are split into seven
     pieces of uneven cluster ranges; the oracle on 384 sampled targets."""
     import oracle
     s = make_surface(RBC, 180)

@@ -513,9 +513,7 @@ def memory_leg(P, dev, log, n_large=2, n_small=62, passes=2, budgets=("full", "o
     probs = [Req(i, r) for i, r in enumerate(stream.requests)]
     total = float(sum(p.N * p.N for p in probs)) * passes
     n_big = max(p.N for p in probs)
-    # resident surface (49 B) + mixed staging (36 B) + the partial sums of the split pair items
-    # of a large request (eight pieces of 24 B) per point
-    per_point = 49 + 36 + 8 * 24
+    per_point = 85                       # resident surface (49 B) + mixed staging (36 B) per point
     all_budgets = {"full": 16 << 30, "one_large": int(1.15 * per_point * n_big)}
     budgets = {k: all_budgets[k] for k in budgets}
     out = {"workload": f"{n_large} capsules N = {n_big} + {n_small} with n in [16, 64] (RBC / "

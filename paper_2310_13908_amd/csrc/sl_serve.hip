@@ -54,16 +54,12 @@ constexpr double kIdleSeconds = 0.02;
 constexpr double kGatherWaitSeconds = 2.0;       // bound on a pair item's wait for its gathers
 constexpr double kPollSeconds = 2e-6;            // spacing of the waves' host-memory polls
 // Pair items of large requests are split over source ranges: one piece per kPieceClusters source
-// clusters, at most kMaxPieces, so that no item holds a wave for long.  The pieces of a target
-// block keep their partial sums in one slot of a pool allocated with the server, and the last
-// piece to finish adds them in piece order.  Slots are dealt round-robin to split blocks as they
-// are published; claims run in ring order and every claimed piece runs to its end, so the blocks
-// with a piece claimed and one still unfinished number at most the resident waves + 1, fewer
-// than kPoolSlots: a slot is free again before its next turn.
+// clusters, at most kMaxPieces, so that no item holds a wave for long.  Each piece keeps its
+// partial sums (24 B per target) in the request's staging, at most kSplitBytes in all, and the
+// last piece of a target block to finish adds them in piece order.
 constexpr int64_t kPieceClusters = 384;
 constexpr int64_t kMaxPieces = 8;
-constexpr int64_t kPoolSlots = 8192;             // > 256 CUs x 16 waves + 1
-constexpr int64_t kPoolSlotDoubles = kMaxPieces * 3 * 128;
+constexpr int64_t kSplitBytes = 64ll << 20;
 
 enum : uint32_t { kItemGather = 0, kItemPair = 1 };
 
@@ -88,6 +84,8 @@ struct ReqDesc {
     int64_t mixed;
     double rho64;                         // mixed: double-precision zone p < rho64
     int64_t pieces;                       // pieces per target block (1: not split)
+    double *part;                         // pieces > 1: [pieces][3][np] partial sums (staging)
+    uint32_t *bdone;                      // pieces > 1: [np / 128] pieces done per target block
 };
 
 struct ServeCtl {                         // host-pinned
@@ -124,8 +122,6 @@ struct ServeArgs {
     uint64_t wait_ticks;                  // longest wait of a pair item for its gathers
     uint64_t poll_ticks;                  // spacing of the host-memory polls
     uint64_t launch_id;                   // distinct for every launch
-    double *pool;                         // [kPoolSlots][kMaxPieces][3][128] partial sums
-    uint32_t *pool_done;                  // [kPoolSlots] pieces done (reset by the last one)
 };
 
 // ------------------------------------------------------------------------------------------
@@ -203,6 +199,11 @@ __device__ void run_gather(const ServeArgs &a, const WorkItem &it)
         gx[p] = vx; gy[p] = vy; gz[p] = vz;
         if (mixed) { gx32[p] = (float)vx; gy32[p] = (float)vy; gz32[p] = (float)vz; }
     }
+    if (field(&d->pieces) > 1) {   // the split pair items' counters of the blocks starting here
+        uint32_t *bdone = field(&d->bdone);
+        for (int64_t k = (int64_t)it.a / kServeBlock + threadIdx.x % kWave; k < (int64_t)it.b / kServeBlock; k += kWave)
+            bdone[k] = 0u;
+    }
     __threadfence();
     if (threadIdx.x % kWave == 0)
         __hip_atomic_fetch_add(&a.dc->gathers_done[it.slot], 1ull, __ATOMIC_RELEASE,
@@ -228,8 +229,7 @@ struct BlockView {
     double *ux, *uy, *uz;
     int64_t np;
     int64_t c_lo, c_hi;                   // the source clusters of this item
-    int64_t t_block;                      // first target of the item's block
-    double *part;                         // split items: this piece's [3][128] partial sums
+    double *part;                         // split items: this piece's [3][np] partial sums
     double scale, gap_far;
     TBlockRec rec;
     DeltaC dc;
@@ -367,10 +367,9 @@ __device__ __forceinline__ void serve_targets(const BlockView &v, int64_t t0, co
             if (v.part) {
                 // written through to memory (system scope, no cache maintenance): the piece that
                 // adds them may run on another XCD
-                const int64_t l = i - v.t_block;
-                st_sys_f64(v.part + l, ox);
-                st_sys_f64(v.part + kServeBlock + l, oy);
-                st_sys_f64(v.part + 2 * kServeBlock + l, oz);
+                st_sys_f64(v.part + i, ox);
+                st_sys_f64(v.part + v.np + i, oy);
+                st_sys_f64(v.part + 2 * v.np + i, oz);
             } else {
                 v.ux[idx] = ox * v.scale;
                 v.uy[idx] = oy * v.scale;
@@ -380,22 +379,21 @@ __device__ __forceinline__ void serve_targets(const BlockView &v, int64_t t0, co
     }
 }
 
-// The last piece of a split target block: the pieces' partial sums (`slot`: [pieces][3][128])
+// The last piece of a split target block: the pieces' partial sums (`part`: [pieces][3][np])
 // added in piece order, scaled and scattered to the caller's arrays.
-__device__ void combine_pieces(const BlockView &v, const double *slot, int64_t pieces, int64_t t0)
+__device__ void combine_pieces(const BlockView &v, const double *part, int64_t pieces, int64_t t0)
 {
     const int lane = threadIdx.x % kWave;
     for (int r = 0; r < kServeR; ++r) {
         const int64_t i = t0 + r * kWave + lane;
         const int32_t idx = v.perm[i];
         if (idx < 0) continue;
-        const int l = r * kWave + lane;
         double ox = 0.0, oy = 0.0, oz = 0.0;
         for (int64_t q = 0; q < pieces; ++q) {
-            const double *pq = slot + q * 3 * kServeBlock;
-            ox += ld_sys_f64(pq + l);
-            oy += ld_sys_f64(pq + kServeBlock + l);
-            oz += ld_sys_f64(pq + 2 * kServeBlock + l);
+            const double *pq = part + q * 3 * v.np;
+            ox += ld_sys_f64(pq + i);
+            oy += ld_sys_f64(pq + v.np + i);
+            oz += ld_sys_f64(pq + 2 * v.np + i);
         }
         v.ux[idx] = ox * v.scale;
         v.uy[idx] = oy * v.scale;
@@ -462,14 +460,12 @@ __device__ void run_pair(const ServeArgs &a, const WorkItem &it, const float4 *t
     v.dc32 = make_delta32(delta, rho64);
     const int64_t t0 = (int64_t)it.a * kServeBlock;
     const int64_t pieces = dfield(&dd->pieces);
-    const int64_t piece = it.kind >> 8;
-    const int64_t pslot = (int64_t)(it.b & (uint32_t)(kPoolSlots - 1));
-    double *const slot = pieces > 1 ? a.pool + pslot * kPoolSlotDoubles : nullptr;
+    const int64_t piece = it.b;
+    double *const part = pieces > 1 ? dfield(&dd->part) : nullptr;
     const int64_t n_cl = v.np / kCluster;
     v.c_lo = piece * n_cl / pieces;
     v.c_hi = (piece + 1) * n_cl / pieces;
-    v.t_block = t0;
-    v.part = slot ? slot + piece * 3 * kServeBlock : nullptr;
+    v.part = part ? part + piece * 3 * v.np : nullptr;
     // One instance per path, so that no path holds another's registers; the mixed path with the
     // double-precision zone, whose pairs hold the most state, takes half of the targets at a time.
     if (!mixed) {
@@ -480,25 +476,23 @@ __device__ void run_pair(const ServeArgs &a, const WorkItem &it, const float4 *t
         serve_targets<true, false, kServeR>(v, t0, tab, st);
     }
     bool wrote_output = true;
-    if (slot) {
+    if (part) {
         // The piece's partial sums were written through to memory; once the wave's stores are
         // complete it counts itself done on the block.  The last piece reads them all from
-        // memory, adds them in piece order, writes the block's output and frees the slot.
+        // memory, adds them in piece order and writes the block's output.
         // The wave's write-through stores are acknowledged before the count: a wait on the
         // vector-memory counter (a workgroup-scope fence would not wait for global stores, and an
         // agent-scope one would write back the whole L2).
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         uint32_t old = 0;
         if (lane == 0)
-            old = __hip_atomic_fetch_add(a.pool_done + pslot, 1u, __ATOMIC_RELAXED,
+            old = __hip_atomic_fetch_add(dfield(&dd->bdone) + it.a, 1u, __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_SYSTEM);
         wrote_output = uni64(old) + 1 == (uint64_t)pieces;
         if (wrote_output) {
             // the partial sums are read after the count (they bypass the caches)
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            combine_pieces(v, slot, pieces, t0);
-            if (lane == 0)
-                __hip_atomic_store(a.pool_done + pslot, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            combine_pieces(v, part, pieces, t0);
         }
     }
     // an item that wrote output releases it (write-back of this XCD's L2) before it counts
@@ -627,7 +621,7 @@ __global__ __launch_bounds__(kServeWaves * kWave) void k_serve(ServeArgs a)
         it.a = (uint32_t)w1;
         it.b = (uint32_t)(w1 >> 32);
         __atomic_thread_fence(__ATOMIC_ACQUIRE);
-        if ((it.kind & 0xffu) == kItemGather)
+        if (it.kind == kItemGather)
             run_gather(a, it);
         else
             run_pair(a, it, sh_tab, stage);
@@ -821,9 +815,6 @@ struct Server {
     uint64_t *done_seq = nullptr;
     DevCounters *dc = nullptr;
     ReqDesc *ddesc = nullptr;             // device copies of the descriptors
-    double *pool = nullptr;               // partial sums of split pair items
-    uint32_t *pool_done = nullptr;
-    uint64_t split_blocks = 0;            // split target blocks published so far
     uint64_t gathers_cum[kMaxSlots] = {};
     uint64_t items_cum[kMaxSlots] = {};
     std::vector<int> free_slots;
@@ -857,13 +848,17 @@ size_t surface_bytes(int64_t np)
 
 int64_t pieces_for(int64_t np)
 {
-    const int64_t p = np / kCluster / kPieceClusters;
-    return p < 2 ? 1 : (p > kMaxPieces ? kMaxPieces : p);
+    int64_t p = np / kCluster / kPieceClusters;
+    p = p > kMaxPieces ? kMaxPieces : p;
+    while (p > 1 && p * 3 * np * 8 > kSplitBytes) --p;
+    return p < 1 ? 1 : p;
 }
 
 size_t staging_bytes(int64_t np, bool mixed)
 {
-    return (size_t)(3 * round_up(np * 8, 256) + (mixed ? 3 * round_up(np * 4, 256) : 0));
+    const int64_t pieces = pieces_for(np);
+    return (size_t)(3 * round_up(np * 8, 256) + (mixed ? 3 * round_up(np * 4, 256) : 0) +
+                    (pieces > 1 ? round_up(pieces * 3 * np * 8, 256) + round_up(np / kServeBlock * 4, 256) : 0));
 }
 
 }  // namespace
@@ -886,10 +881,7 @@ sl_status Server::init(sl_ctx *c)
     memset((void *)done_seq, 0, sizeof(uint64_t) * kMaxSlots);
     SL_HIP(hipMalloc((void **)&dc, sizeof(DevCounters)));
     SL_HIP(hipMalloc((void **)&ddesc, sizeof(ReqDesc) * kMaxSlots));
-    SL_HIP(hipMalloc((void **)&pool, sizeof(double) * kPoolSlots * kPoolSlotDoubles));
-    SL_HIP(hipMalloc((void **)&pool_done, sizeof(uint32_t) * kPoolSlots));
     SL_HIP(hipMemsetAsync(dc, 0, sizeof(DevCounters), aux));
-    SL_HIP(hipMemsetAsync(pool_done, 0, sizeof(uint32_t) * kPoolSlots, aux));
     size_t bytes = ctx->budget;
     SL_HIP(hipMalloc((void **)&arena_mem, bytes));
     SL_HIP(hipStreamSynchronize(aux));
@@ -914,8 +906,6 @@ void Server::shutdown()
     if (arena_mem) (void)hipFree(arena_mem);
     if (dc) (void)hipFree(dc);
     if (ddesc) (void)hipFree(ddesc);
-    if (pool) (void)hipFree(pool);
-    if (pool_done) (void)hipFree(pool_done);
     if (ctl) (void)hipHostFree(ctl);
     if (ring) (void)hipHostFree(ring);
     if (desc) (void)hipHostFree(desc);
@@ -990,11 +980,17 @@ void Server::admit_locked()
         if (r.mixed) {
             d.gx32 = (float *)p; p += round_up(s.np * 4, 256);
             d.gy32 = (float *)p; p += round_up(s.np * 4, 256);
-            d.gz32 = (float *)p;
+            d.gz32 = (float *)p; p += round_up(s.np * 4, 256);
         } else {
             d.gx32 = d.gy32 = d.gz32 = nullptr;
         }
         d.pieces = pieces;
+        d.part = nullptr;
+        d.bdone = nullptr;
+        if (pieces > 1) {
+            d.part = (double *)p; p += round_up(pieces * 3 * s.np * 8, 256);
+            d.bdone = (uint32_t *)p;
+        }
         d.n = s.n;
         d.np = s.np;
         d.delta = s.delta;
@@ -1012,14 +1008,9 @@ void Server::admit_locked()
             const int64_t b = a + kGatherChunk < s.np ? a + kGatherChunk : s.np;
             ring[(tail + k) & (kRingCap - 1)] = WorkItem{(uint32_t)slot, kItemGather, (uint32_t)a, (uint32_t)b};
         }
-        // split blocks: the piece in the kind's upper bits, the block's pool slot turn in b
-        for (uint64_t k = 0; k < n_pair; ++k) {
-            const uint64_t q = k % (uint64_t)pieces;
-            if (pieces > 1 && q == 0) split_blocks += 1;
+        for (uint64_t k = 0; k < n_pair; ++k)
             ring[(tail + n_gather + k) & (kRingCap - 1)] =
-                WorkItem{(uint32_t)slot, kItemPair | (uint32_t)(q << 8), (uint32_t)(k / pieces),
-                         pieces > 1 ? (uint32_t)(split_blocks - 1) : 0u};
-        }
+                WorkItem{(uint32_t)slot, kItemPair, (uint32_t)(k / pieces), (uint32_t)(k % pieces)};
         tail += n_gather + n_pair;
         __atomic_store_n(&ctl->tail, tail, __ATOMIC_RELEASE);
         active.push_back(r.id);
@@ -1040,7 +1031,7 @@ sl_status Server::ensure_kernel_locked()
     }
     ServeArgs a{ctl, ring, desc, ddesc, done_seq, dc,
                 (uint64_t)(kIdleSeconds * clock_hz), (uint64_t)(kGatherWaitSeconds * clock_hz),
-                (uint64_t)(kPollSeconds * clock_hz) + 1, stats.kernel_launches + 1, pool, pool_done};
+                (uint64_t)(kPollSeconds * clock_hz) + 1, stats.kernel_launches + 1};
     // All waves resident at once (so that they share one idle clock), at most kServeWavesPerSimd
     // per SIMD.
     int per_cu = 0;   // workgroups of kServeWaves waves

@@ -9,7 +9,8 @@ import ctypes
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libstokeslet.so")
+# SL_LIB may name another build of the same library (the host-sanitized one, for its tests).
+LIB_PATH = os.environ.get("SL_LIB") or os.path.join(_PKG, "libstokeslet.so")
 
 SL_OK, SL_EINVAL, SL_ENOMEM, SL_EBUSY, SL_EHIP, SL_ENOTFOUND, SL_ETIMEDOUT = 0, -1, -2, -3, -4, -5, -6
 SL_FP64, SL_MIXED = 0, 1

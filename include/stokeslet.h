@@ -84,7 +84,7 @@ const char *sl_last_error(const sl_ctx *ctx);
  *   2 beyond).
  * SL_PARAM_WAVES_PER_SIMD: granularity of the pair kernels' work items: the sources are split
  *   until there are about this many items per SIMD, into at most 128 ways per target block (64
- *   in SL_MIXED) (1..64; default 64). */
+ *   in SL_MIXED) (1..256; default 128). */
 typedef enum {
     SL_PARAM_RHO64 = 0,
     SL_PARAM_KERNEL_TIMING = 1,

@@ -346,8 +346,8 @@ sl_status sl_set_param(sl_ctx *ctx, sl_param key, double value)
         return SL_OK;
     }
     if (key == SL_PARAM_WAVES_PER_SIMD) {
-        if (!(value >= 1.0 && value <= 64.0) || value != (double)(int)value)
-            return fail(SL_EINVAL, "sl_set_param: waves per SIMD is an integer in 1..64");
+        if (!(value >= 1.0 && value <= 256.0) || value != (double)(int)value)
+            return fail(SL_EINVAL, "sl_set_param: waves per SIMD is an integer in 1..256");
         std::lock_guard<std::mutex> l(ctx->mu);
         ctx->waves_per_simd = (int)value;
         return SL_OK;

@@ -210,7 +210,7 @@ struct sl_ctx {
     size_t budget = 0;
     double rho64 = 0.0;
     int targets_per_lane = 0;   // 0: chosen per call
-    int waves_per_simd = 64;
+    int waves_per_simd = 128;
     std::mutex mu;
     sl::Server *server = nullptr;
     // pair-kernel timing (SL_PARAM_KERNEL_TIMING)

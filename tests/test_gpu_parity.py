@@ -352,7 +352,7 @@ def test_launch_shapes(precision, rho64):
     with P.Context(0) as c:
         c.set_rho64(rho64)
         for R in (1, 2, 4):
-            for wps in (1, 3, 16, 64):
+            for wps in (1, 3, 16, 64, 256):
                 P.check(P.sl_set_param(c.ptr, P.SL_PARAM_TARGETS_PER_LANE, float(R)))
                 P.check(P.sl_set_param(c.ptr, P.SL_PARAM_WAVES_PER_SIMD, float(wps)))
                 u = gpu_eval(c, s.X, s.w, f, d, precision=precision)

@@ -552,8 +552,13 @@ def memory_leg(P, dev, log, n_large=2, n_small=62, passes=2, budgets=("full", "o
                             return
 
                 t0 = time.perf_counter()
+                next_note = 20.0
                 for k in range(passes):
                     for i, p in enumerate(probs):
+                        if time.perf_counter() - t0 > next_note:
+                            log(f"[bench] memory stream {bname} {prec}: pass {k}, capsule {i} of "
+                                f"{len(probs)} after {next_note:.0f} s")
+                            next_note += 20.0
                         np_i = -(-p.N // 256) * 256   # padded nodes: 49 B each resident
                         if i in resident:
                             resident.move_to_end(i)
@@ -583,6 +588,10 @@ def memory_leg(P, dev, log, n_large=2, n_small=62, passes=2, budgets=("full", "o
                 while inflight:
                     rid0, c0, _ = inflight.popleft()
                     ctx.wait(rid0, 120.0)
+                    if time.perf_counter() - t0 > next_note:
+                        log(f"[bench] memory stream {bname} {prec}: draining, {len(inflight)} in "
+                            f"flight after {next_note:.0f} s")
+                        next_note += 20.0
                 dt = time.perf_counter() - t0
             out[f"{bname}_{prec}"] = {"budget_bytes": budget, "seconds": round(dt, 3),
                                       "gpair_s": round(total / dt / 1e9, 2),

@@ -250,10 +250,11 @@ sl_status sl_eval_fmm(sl_ctx *ctx, sl_precision prec, int64_t n, const double *x
  *
  * sl_submit enqueues u = S[f] on a resident surface: fx, fy, fz (density) and ux, uy, uz
  * (output) are caller device arrays of the surface's n, valid until the request completes.
- * The request's work (one item per block of targets) joins the queue of a single persistent
- * kernel that serves every in-flight request; requests submitted while others run are
- * interleaved with them on the device.  Each request's result is bit-identical to the same
- * request served alone.  A request is admitted at once when its staging memory fits the
+ * The request's work (one item per block of 128 targets; on a surface of at least 49,152
+ * points, up to eight items per block over source ranges, whose partial sums the request's
+ * staging holds) joins the queue of a single persistent kernel that serves every in-flight
+ * request; requests submitted while others run are interleaved with them on the device.  Each
+ * request's result is bit-identical to the same request served alone.  A request is admitted at once when its staging memory fits the
  * budget, otherwise it waits (first in, first out) until memory is returned; SL_EBUSY only if
  * its staging exceeds the whole budget.
  * Thread-safe.
@@ -270,8 +271,9 @@ sl_status sl_submit(sl_ctx *ctx, uint64_t handle, sl_precision prec,
                     const double *fx, const double *fy, const double *fz, double mu,
                     double *ux, double *uy, double *uz, uint64_t *request);
 sl_status sl_poll(sl_ctx *ctx, uint64_t request, int *done);
-/* Device memory a request on surface `handle` holds from admission to completion (its staging),
- * so that a client managing its own budget can make room before submitting.  SL_ENOTFOUND for an
+/* Device memory a request on surface `handle` holds from admission to completion (its staging:
+ * the packed density, and for a surface large enough for split work items their partial sums,
+ * at most 64 MiB), so that a client managing its own budget can make room before submitting.  SL_ENOTFOUND for an
  * unknown or released handle. */
 sl_status sl_request_bytes(sl_ctx *ctx, uint64_t handle, sl_precision prec, uint64_t *bytes);
 sl_status sl_wait(sl_ctx *ctx, uint64_t request, double timeout_s);

@@ -9,8 +9,10 @@
 //  * Work items live in a ring of host-pinned, fine-grained memory: (slot, kind, a, b).
 //    kind GATHER packs g = w f for points [a, b) of the request into its staging (sorted order);
 //    kind PAIR sums every source of the surface for target block a (128 targets) and writes
-//    u = S[f] for those targets.  A request is published as its gather items followed by its
-//    pair items; pair items wait for the request's gathers (which were claimed earlier, so the
+//    u = S[f] for those targets; on a large surface, piece b of P sums the source clusters
+//    [b n / P, (b + 1) n / P) into the request's staging and the block's last piece adds the P
+//    partial sums in piece order and writes u.  A request is published as its gather items
+//    followed by its pair items; pair items wait for the request's gathers (which were claimed earlier, so the
 //    wait is bounded).  The request's first gather item copies its descriptor from host memory
 //    into device memory, where the pair items read it (one PCIe read per item instead of ~30).
 //  * One persistent kernel serves all requests: each wavefront claims the next item with a CAS
@@ -26,8 +28,9 @@
 //    cache, which is only invalidated at kernel launch); each lane loads one source of a
 //    cluster into the wave's own LDS area, and the source loop reads each record back at one
 //    address across the wave (an LDS broadcast), so the arithmetic takes it as a vector operand.
-//  * Each target's sum runs in a fixed order (clusters ascending, one accumulator set) whatever
-//    else is in flight, so a request's result is bit-identical alone and in any mix.
+//  * Each target's sum runs in a fixed order (clusters ascending, one accumulator set per piece,
+//    the pieces added in order) whatever else is in flight, so a request's result is
+//    bit-identical alone and in any mix.
 #include <math.h>
 #include <string.h>
 

@@ -56,6 +56,7 @@ constexpr int kServeWaves = 4;                     // waves per workgroup (one s
 constexpr double kIdleSeconds = 0.02;
 constexpr double kGatherWaitSeconds = 2.0;       // bound on a pair item's wait for its gathers
 constexpr double kPollSeconds = 2e-6;            // spacing of the waves' host-memory polls
+constexpr double kRegisterWaitSeconds = 0.005;   // a registration's packing beside a busy kernel
 // Pair items of large requests are split over source ranges: one piece per kPieceClusters source
 // clusters, at most kMaxPieces, so that no item holds a wave for long.  Each piece keeps its
 // partial sums (24 B per target) in the request's staging, at most kSplitBytes in all, and the
@@ -1168,7 +1169,6 @@ sl_status sl_surface_register(sl_ctx *ctx, int64_t n, const double *x, const dou
     sf.n = n;
     sf.np = np;
     sf.delta = delta;
-    bool drain = false;
     {
         std::lock_guard<std::mutex> l(s->mu);
         // Requests waiting for memory go first: a surface does not overtake them.
@@ -1177,31 +1177,14 @@ sl_status sl_surface_register(sl_ctx *ctx, int64_t n, const double *x, const dou
         sf.mem = s->arena.alloc(surface_bytes(np));
         if (!sf.mem)
             return fail(SL_EBUSY, "sl_surface_register: surface does not fit the HBM budget");
-        // The persistent kernel holds every wave slot, so the packing kernels below could only
-        // start once it idles out.  Ask it to exit as soon as the queued work is done instead, and
-        // keep it from being relaunched until the surface is packed.
+        // No relaunch of the persistent kernel until the surface is packed.
         s->registering += 1;
-        if (s->kernel_launched && hipEventQuery(s->kdone) == hipErrorNotReady) {
-            __atomic_store_n(&s->ctl->stop, 1ull, __ATOMIC_RELEASE);
-            drain = true;
-        }
     }
     auto done_registering = [&]() {
         std::lock_guard<std::mutex> l(s->mu);
         if (--s->registering == 0) __atomic_store_n(&s->ctl->stop, 0ull, __ATOMIC_RELEASE);
         s->cv.notify_all();
     };
-    if (drain) {
-        const hipError_t ed = hipEventSynchronize(s->kdone);
-        if (ed != hipSuccess) {
-            {
-                std::lock_guard<std::mutex> l(s->mu);
-                s->arena.release(sf.mem);
-            }
-            done_registering();
-            return hip_fail(ed, "sl_surface_register: waiting for the serving kernel");
-        }
-    }
     char *p = sf.mem;
     auto take = [&](int64_t bytes) { char *q = p; p += round_up(bytes, 256); return q; };
     sf.x = (double *)take(np * 8); sf.y = (double *)take(np * 8); sf.z = (double *)take(np * 8);
@@ -1229,6 +1212,30 @@ sl_status sl_surface_register(sl_ctx *ctx, int64_t n, const double *x, const dou
         e = hipGetLastError();
     }
     if (scratch) (void)hipFreeAsync(scratch, s->aux);
+    // The packing kernels run beside a busy persistent kernel where the device has room for
+    // them.  If they have not finished after kRegisterWaitSeconds, ask the persistent kernel to
+    // exit once its queued work is done, so that they get the device.
+    if (e == hipSuccess) {
+        const auto t0 = std::chrono::steady_clock::now();
+        hipError_t q;
+        while ((q = hipStreamQuery(s->aux)) == hipErrorNotReady &&
+               std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() < kRegisterWaitSeconds)
+            std::this_thread::sleep_for(std::chrono::microseconds(50));
+        if (q == hipErrorNotReady) {
+            bool drain = false;
+            {
+                std::lock_guard<std::mutex> l(s->mu);
+                if (s->kernel_launched && hipEventQuery(s->kdone) == hipErrorNotReady) {
+                    __atomic_store_n(&s->ctl->stop, 1ull, __ATOMIC_RELEASE);
+                    drain = true;
+                }
+            }
+            if (drain) {
+                const hipError_t ed = hipEventSynchronize(s->kdone);
+                if (ed != hipSuccess) e = ed;
+            }
+        }
+    }
     const hipError_t es = hipStreamSynchronize(s->aux);
     if (e == hipSuccess) e = es;
     done_registering();

@@ -34,8 +34,10 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <map>
+#include <unordered_set>
 
 #include "sl_internal.h"
 
@@ -732,6 +734,23 @@ public:
         }
         return nullptr;
     }
+    // The block at p of `bytes` (p inside a free block that holds it): undoes a release.
+    char *alloc_at(char *p, size_t bytes)
+    {
+        bytes = (size_t)round_up((int64_t)bytes, 256);
+        const size_t off = (size_t)(p - base);
+        auto it = free_.upper_bound(off);
+        if (it == free_.begin()) return nullptr;
+        --it;
+        const size_t fo = it->first, fl = it->second;
+        if (off < fo || off + bytes > fo + fl) return nullptr;
+        free_.erase(it);
+        if (off > fo) free_[fo] = off - fo;
+        if (off + bytes < fo + fl) free_[off + bytes] = fo + fl - off - bytes;
+        used += bytes;
+        sizes_[off] = bytes;
+        return p;
+    }
     void release(char *p)
     {
         const size_t off = (size_t)(p - base);
@@ -775,6 +794,21 @@ struct Surface {
     int refs = 0;
     bool released = false;
 };
+
+// The arrays of a resident surface inside its arena block (as written by the registration).
+void surface_layout(Surface &sf, char *mem)
+{
+    const int64_t np = sf.np;
+    sf.mem = mem;
+    char *p = mem;
+    auto take = [&](int64_t bytes) { char *q = p; p += round_up(bytes, 256); return q; };
+    sf.x = (double *)take(np * 8); sf.y = (double *)take(np * 8); sf.z = (double *)take(np * 8);
+    sf.w = (double *)take(np * 8);
+    sf.x32 = (float *)take(np * 4); sf.y32 = (float *)take(np * 4); sf.z32 = (float *)take(np * 4);
+    sf.perm = (int32_t *)take(np * 4);
+    sf.sphere = (double4 *)take(np / kCluster * (int64_t)sizeof(double4));
+    sf.tbr = (TBlockRec *)take(np / kServeBlock * (int64_t)sizeof(TBlockRec));
+}
 
 enum class ReqState { Pending, Active, Done, Failed };
 
@@ -836,6 +870,7 @@ struct Server {
     void loop();
     void complete_locked();
     void admit_locked();
+    bool compact_locked();
     sl_status ensure_kernel_locked();
     void free_surface_locked(uint64_t h);
 };
@@ -952,6 +987,56 @@ void Server::complete_locked()
     if (any) done_cv.notify_all();
 }
 
+// Moves the resident surfaces that no admitted request reads toward the start of the arena, so
+// that the free bytes come together (first fit can otherwise leave a request that the free
+// bytes would hold waiting for good).  Each copy goes through a scratch buffer (source and
+// destination may overlap) on the auxiliary stream, and the call waits for them: surfaces of
+// pending requests are not read before admission, idle ones not at all.  Returns whether
+// anything moved.
+bool Server::compact_locked()
+{
+    std::unordered_set<uint64_t> pinned;
+    for (uint64_t id : active) pinned.insert(reqs[id].surf);
+    std::vector<std::pair<char *, uint64_t>> order;
+    for (auto &kv : surfaces)
+        if (!pinned.count(kv.first)) order.emplace_back(kv.second.mem, kv.first);
+    std::sort(order.begin(), order.end());
+    bool moved = false;
+    hipError_t e = hipSuccess;
+    for (auto &o : order) {
+        Surface &sf = surfaces[o.second];
+        const size_t bytes = surface_bytes(sf.np);
+        char *old = sf.mem;
+        arena.release(old);
+        char *nw = arena.alloc(bytes);   // the block just released fits, at the latest
+        if (nw == old) continue;
+        void *tmp = nullptr;
+        e = ws_alloc(ctx, &tmp, bytes, aux);
+        if (e == hipSuccess) e = hipMemcpyAsync(tmp, old, bytes, hipMemcpyDeviceToDevice, aux);
+        if (e == hipSuccess) e = hipMemcpyAsync(nw, tmp, bytes, hipMemcpyDeviceToDevice, aux);
+        if (tmp) (void)hipFreeAsync(tmp, aux);
+        if (e != hipSuccess) {
+            // put the block back where it was (the data did not move)
+            arena.release(nw);
+            char *back = arena.alloc_at(old, bytes);
+            (void)back;
+            break;
+        }
+        surface_layout(sf, nw);
+        moved = true;
+    }
+    if (moved) {
+        const hipError_t es = hipStreamSynchronize(aux);
+        if (e == hipSuccess) e = es;
+    }
+    if (e != hipSuccess && fatal == SL_OK) {
+        fatal = hip_fail(e, "serving: compacting the arena");
+        fatal_msg = sl_last_error(ctx);
+        done_cv.notify_all();
+    }
+    return moved;
+}
+
 void Server::admit_locked()
 {
     while (!pending.empty()) {
@@ -962,7 +1047,10 @@ void Server::admit_locked()
         const uint64_t n_pair = (uint64_t)(s.np / kServeBlock * pieces);
         const uint64_t claimed = __atomic_load_n(&ctl->claimed, __ATOMIC_ACQUIRE);
         if (free_slots.empty() || tail + n_gather + n_pair - claimed > kRingCap) break;
-        char *st = arena.alloc(staging_bytes(s.np, r.mixed));
+        const size_t need = staging_bytes(s.np, r.mixed);
+        char *st = arena.alloc(need);
+        // first fit can leave the free bytes in pieces none of which holds the staging
+        if (!st && arena.size - arena.used >= need && compact_locked()) st = arena.alloc(need);
         if (!st) break;
         const int slot = free_slots.back();
         free_slots.pop_back();
@@ -1185,14 +1273,7 @@ sl_status sl_surface_register(sl_ctx *ctx, int64_t n, const double *x, const dou
         if (--s->registering == 0) __atomic_store_n(&s->ctl->stop, 0ull, __ATOMIC_RELEASE);
         s->cv.notify_all();
     };
-    char *p = sf.mem;
-    auto take = [&](int64_t bytes) { char *q = p; p += round_up(bytes, 256); return q; };
-    sf.x = (double *)take(np * 8); sf.y = (double *)take(np * 8); sf.z = (double *)take(np * 8);
-    sf.w = (double *)take(np * 8);
-    sf.x32 = (float *)take(np * 4); sf.y32 = (float *)take(np * 4); sf.z32 = (float *)take(np * 4);
-    sf.perm = (int32_t *)take(np * 4);
-    sf.sphere = (double4 *)take(np / kCluster * (int64_t)sizeof(double4));
-    sf.tbr = (TBlockRec *)take(np / kServeBlock * (int64_t)sizeof(TBlockRec));
+    surface_layout(sf, sf.mem);
 
     PackScratch ps;
     char *scratch = nullptr;

@@ -141,6 +141,45 @@ def test_split_request_matches_oracle_and_mix(ctx, surfaces, split_case):
         assert np.array_equal(alone, in_mix)
 
 
+def test_fragmented_arena_is_compacted():
+    """First fit can leave the free bytes in pieces that each are too small for a request's
+    staging although together they hold it: surfaces A, B, C fill a budget up to a tail smaller
+    than C's staging, A (smaller than that staging too) is released, and a request on C must
+    still be admitted (the idle and pending surfaces move down), with correct results on the moved
+    surfaces."""
+    import oracle
+    import paper_2310_13908_amd as P
+    shapes = [(RBC, 24), (SPHERE, 16), (ELLIPSOID_SERVING, 40)]
+    data = []
+    for k, (shape, n) in enumerate(shapes):
+        sf = make_surface(shape, n)
+        data.append((sf, sh_force(sf.x0, 700 + k), 2 * math.pi / (n + 1)))
+    # sizes of the three surfaces and of C's staging, from a roomy context
+    with P.Context(0, hbm_budget_bytes=64 << 20) as c:
+        sizes = []
+        for sf, f, d in data:
+            before = int(c.stats().bytes_admitted)
+            h = c.register_surface(dev_t(sf.X), dev_t(sf.w), d)
+            sizes.append(int(c.stats().bytes_admitted) - before)
+        staging = c.request_bytes(h, "mixed")
+    a, b, cc = sizes
+    assert a < staging
+    tail = staging - a // 2 // 256 * 256
+    with P.Context(0, hbm_budget_bytes=a + b + cc + tail) as c:
+        hs = [c.register_surface(dev_t(sf.X), dev_t(sf.w), d) for sf, f, d in data]
+        c.release_surface(hs[0])
+        sf, f, d = data[2]
+        rid, _ = c.submit(hs[2], dev_t(f), mu=0.8, precision="mixed")
+        u = c.wait(rid, 60.0).cpu().numpy()
+        ref = oracle.single_layer(sf.X, sf.w, f, d, mu=0.8)
+        assert eps(u, ref) < TOL["mixed"]
+        sf, f, d = data[1]
+        rid, _ = c.submit(hs[1], dev_t(f), mu=0.8, precision="fp64")
+        u = c.wait(rid, 60.0).cpu().numpy()
+        ref = oracle.single_layer(sf.X, sf.w, f, d, mu=0.8)
+        assert eps(u, ref) < TOL["fp64"]
+
+
 def test_admission_under_small_budget(surfaces, refs):
     """Budget that holds the surfaces but only a couple of requests' staging at a time:
     every request still completes, correctly, and the admitted bytes stay within the budget."""

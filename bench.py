@@ -643,7 +643,8 @@ def main():
                     help="skip the memory-admitted stream leg")
     ap.add_argument("--c5-full", action="store_true",
                     help="run the memory-admitted stream at its stated size (64 capsules of "
-                         "N = 1,572,864 and 2,000 small ones, one pass; several minutes)")
+                         "N = 1,572,864 and 2,000 small ones, three passes, with the full budget "
+                         "and with one that holds a single large capsule; about 20 minutes)")
     ap.add_argument("--workload", choices=["c3", "c2"], default="c3",
                     help="workload of the timed step: RBC 6x256x256 (the headline) or RBC 6x64x64 "
                          "(for counter runs of the smaller case)")
@@ -732,8 +733,8 @@ def main():
         if not args.no_memory_stream:
             line["memory_stream_sample"] = memory_leg(P, dev, log)
     if args.c5_full:
-        line["memory_stream_full"] = memory_leg(P, dev, log, n_large=64, n_small=2000, passes=1,
-                                                budgets=("full",))
+        line["memory_stream_full"] = memory_leg(P, dev, log, n_large=64, n_small=2000, passes=3,
+                                                budgets=("full", "one_large"))
 
     if args.copy_bytes:
         a = torch.empty(args.copy_bytes // 8, dtype=torch.float64, device=dev).fill_(1.0)

@@ -23,6 +23,14 @@ Chebyshev nodes of the interval of 40-digit values, rounded to single precision.
 and K2 = F2/delta^3 then take one table row, three fused multiply-adds per factor and no
 transcendental instruction; there is no cancellation anywhere in q.
 
+The double-precision kernels evaluate the whole zone q < 6.9^2 from one table of polynomials of
+degree TAB64_DEG: interval 0 is 0 <= q < 1, where F1 and F2 are taken (as above, entire in q);
+interval 1 + 4 e + j covers q in 2^e [1 + j/4, 1 + (j+1)/4), e = 0..5, j = 0..3, where s1 and s2
+themselves are taken (they stay away from their branch point at q = 0 there).  On each interval,
+with centre m and half width h, the polynomial in x = (q - m)/h in [-1, 1] interpolates 40-digit
+values at Chebyshev nodes; K1 = F1/delta or s1/r, K2 = F2/delta^3 or s2/r^3.  One branch and one
+table row per pair, instead of a series for q < 1 and an exp/erfc form beyond.
+
 Run: python gen_smoothing.py  (rewrites sl_smoothing_coeffs.h next to this file and prints the
 achieved double-precision error of every approximation).
 """
@@ -48,6 +56,9 @@ EXP_DEG = 11            # degree of e^x on |x| <= ln2/2
 # 0 <= q < TAB32_QMAX (p < 5, where s = 1 to single precision).
 TAB32_N = 256
 TAB32_QMAX = 25.0
+# Double precision: degree and intervals of the table (see above).
+TAB64_DEG = 13
+TAB64_QMAX = 6.9 ** 2
 
 
 def cheb_nodes(a, b, n):
@@ -120,6 +131,60 @@ def tab32_coeffs():
         t1.append([float(np.float32(float(c))) for c in c1])
         t2.append([float(np.float32(float(c))) for c in c2])
     return t1, t2
+
+
+def tab64_intervals():
+    iv = [(0.0, 1.0)]
+    for e in range(6):
+        for j in range(4):
+            a, b = 2.0 ** e * (1 + j / 4), 2.0 ** e * (1 + (j + 1) / 4)
+            if a < TAB64_QMAX:
+                iv.append((a, b))
+    return iv
+
+
+def S_exact(q):
+    return s_exact(mp.sqrt(mp.mpf(q)))
+
+
+def tab64_rows():
+    """Per interval: centre, 1/half width, then (c1_k, c2_k) for k = TAB64_DEG .. 0 (Horner order)."""
+    n = TAB64_DEG + 1
+    xs = [mp.cos(mp.pi * (j + mp.mpf(1) / 2) / n) for j in range(n)]
+    A = mp.matrix([[x ** i for i in range(n)] for x in xs])
+    rows = []
+    for idx, (a, b) in enumerate(tab64_intervals()):
+        f = F_exact if idx == 0 else S_exact
+        m, h = (mp.mpf(a) + mp.mpf(b)) / 2, (mp.mpf(b) - mp.mpf(a)) / 2
+        vals = [f(m + h * x) for x in xs]
+        c1 = mp.lu_solve(A, mp.matrix([v[0] for v in vals]))
+        c2 = mp.lu_solve(A, mp.matrix([v[1] for v in vals]))
+        row = [float(m), float(1 / h)]
+        for k in range(TAB64_DEG, -1, -1):
+            row += [float(c1[k]), float(c2[k])]
+        rows.append(row)
+    return rows
+
+
+def tab64_error(rows):
+    """Worst relative error of F (interval 0) and absolute error of s (the others), double
+    evaluation with two roundings per Horner step (the device fuses them)."""
+    worst = 0.0
+    for idx, (a, b) in enumerate(tab64_intervals()):
+        f = F_exact if idx == 0 else S_exact
+        r = rows[idx]
+        for q in np.linspace(a, min(b, TAB64_QMAX), 40):
+            x = (q - r[0]) * r[1]
+            p1, p2 = r[2], r[3]
+            for k in range(1, TAB64_DEG + 1):
+                p1 = p1 * x + r[2 + 2 * k]
+                p2 = p2 * x + r[3 + 2 * k]
+            e1, e2 = (float(v) for v in f(q))
+            d1, d2 = abs(p1 - e1), abs(p2 - e2)
+            if idx == 0:
+                d1, d2 = d1 / abs(e1), d2 / abs(e2)
+            worst = max(worst, d1, d2)
+    return worst
 
 
 def tab32_error(t1, t2):
@@ -214,6 +279,8 @@ def main():
     rep = check(c1, c2, gc, ec)
     t1, t2 = tab32_coeffs()
     rep["tab32_rel_F1"], rep["tab32_rel_F2"] = tab32_error(t1, t2)
+    r64 = tab64_rows()
+    rep["tab64_err"] = tab64_error(r64)
     for k, v in rep.items():
         print(f"{k}: {v:.3e}")
     lines = [
@@ -249,6 +316,15 @@ def main():
         f"constexpr float kTab32QMax = {TAB32_QMAX!r}f;",
         "constexpr float kTab32[2 * kTab32N][4] = {",
         *["    {" + ", ".join(f"{c:.9e}f" for c in row) + "}," for row in t1 + t2],
+        "};",
+        "// Double precision, 0 <= q < 6.9^2: row i = {centre, 1/half width, (c1, c2) of x^kTab64Deg, ...,",
+        "// (c1, c2) of x^0}, x = (q - centre)/half width; row 0: F1, F2 on [0, 1); row 1 + 4 e + j: s1, s2 on",
+        f"// 2^e [1 + j/4, 1 + (j+1)/4).  Max error (relative for F, absolute for s) {rep['tab64_err']:.2e}.",
+        f"constexpr int kTab64Deg = {TAB64_DEG};",
+        f"constexpr int kTab64N = {len(r64)};",
+        "constexpr int kTab64Row = 2 * (kTab64Deg + 2);   // doubles per row",
+        "constexpr double kTab64[kTab64N][kTab64Row] = {",
+        *["    {" + ", ".join(f"{c:.17e}" for c in row) + "}," for row in r64],
         "};",
         "}  // namespace sl",
         "",

@@ -162,11 +162,102 @@ __device__ __forceinline__ void near_pair64(double tx, double ty, double tz,
     az = fma(K1, gz, fma(c, dz, az));
 }
 
-// One source against the R targets of a lane, in double precision: near_pair64 for each target,
-// with the smoothing evaluated for all R targets together wherever one lane of the wavefront
-// needs it, so that each polynomial coefficient is materialized once for R targets.
+// The double-precision smoothing table (kTab64) in LDS, copied by the threads of a workgroup (the
+// caller synchronizes afterwards): per row, {centre, 1/half width}, then the pairs (c1, c2) from
+// the highest power down, as double2.
+constexpr int kTab64Row2 = kTab64Row / 2;
+constexpr int kTab64Size2 = kTab64N * kTab64Row2;
+
+__device__ __forceinline__ void load_tab64(double2 *tab)
+{
+    for (int i = threadIdx.x; i < kTab64Size2; i += blockDim.x)
+        tab[i] = make_double2(kTab64[i / kTab64Row2][2 * (i % kTab64Row2)],
+                              kTab64[i / kTab64Row2][2 * (i % kTab64Row2) + 1]);
+}
+
+// Table row of q = (r/delta)^2: 0 for q < 1, else 1 + 4 e + j for q in 2^e [1 + j/4, 1 + (j+1)/4)
+// (exponent and top two mantissa bits); anything past the table, infinity included, takes the
+// last row, and the caller selects those lanes out.
+__device__ __forceinline__ int tab64_row(double q)
+{
+    if (!(q >= 1.0)) return 0;
+    const int e = __builtin_amdgcn_frexp_exp(q) - 1;
+    const int j = (int)((__builtin_amdgcn_frexp_mant(q) - 0.5) * 8.0);
+    const int i = 1 + 4 * e + j;
+    return (i >= 1 && i < kTab64N) ? i : kTab64N - 1;
+}
+
+// Row 0: F1(q) = s1/p and F2(q) = s2/p^3; other rows: s1 and s2; a polynomial of degree
+// kTab64Deg in the row's local variable, Horner with fused multiply-adds.
+__device__ __forceinline__ void smoothing64(double q, const double2 *tab, int row, double &p1, double &p2)
+{
+    const double2 *r = tab + row * kTab64Row2;
+    const double2 h = r[0];
+    const double x = (q - h.x) * h.y;
+    double2 c = r[1];
+    p1 = c.x;
+    p2 = c.y;
+#pragma unroll
+    for (int k = 2; k < kTab64Row2; ++k) {
+        c = r[k];
+        p1 = fma(p1, x, c.x);
+        p2 = fma(p2, x, c.y);
+    }
+}
+
+// One source against the R targets of a lane, in double precision, the smoothing from the table
+// in LDS (`tab`, load_tab64) for every lane within 6.9 delta, evaluated wherever one lane of the
+// wavefront needs it: one branch, one table row a pair.
 template <int R>
 __device__ __forceinline__ void near_pairs64(const double (&tx)[R], const double (&ty)[R],
+                                             const double (&tz)[R], double sx, double sy, double sz,
+                                             double gx, double gy, double gz, const DeltaC (&dc)[R],
+                                             const double2 *tab, double (&ax)[R], double (&ay)[R],
+                                             double (&az)[R])
+{
+    double dx[R], dy[R], dz[R], r2[R], ri[R], q[R], K1[R], K2[R];
+    bool sm[R];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        dx[r] = tx[r] - sx;
+        dy[r] = ty[r] - sy;
+        dz[r] = tz[r] - sz;
+        r2[r] = fma(dx[r], dx[r], fma(dy[r], dy[r], dz[r] * dz[r]));
+        ri[r] = rsqrt64(r2[r] > 0.0 ? r2[r] : 1.0);
+        K1[r] = ri[r];
+        K2[r] = ri[r] * ri[r] * ri[r];
+        q[r] = r2[r] * dc[r].id2;
+        sm[r] = r2[r] < dc[r].cut2;
+        any = any || sm[r];
+    }
+    if (__builtin_amdgcn_ballot_w64(any)) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int row = tab64_row(q[r]);
+            double p1, p2;
+            smoothing64(q[r], tab, row, p1, p2);
+            const double k1 = row == 0 ? p1 * dc[r].id : ri[r] * p1;
+            const double k2 = row == 0 ? p2 * dc[r].id3 : (ri[r] * ri[r] * ri[r]) * p2;
+            K1[r] = sm[r] ? k1 : K1[r];
+            K2[r] = sm[r] ? k2 : K2[r];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double gd = fma(gx, dx[r], fma(gy, dy[r], gz * dz[r]));
+        const double c = gd * K2[r];
+        ax[r] = fma(K1[r], gx, fma(c, dx[r], ax[r]));
+        ay[r] = fma(K1[r], gy, fma(c, dy[r], ay[r]));
+        az[r] = fma(K1[r], gz, fma(c, dz[r], az[r]));
+    }
+}
+
+// The same with the series for q < 1 and the exp/erfc form beyond, each evaluated wherever one
+// lane of the wavefront needs it (no table): the per-target-delta kernels, whose registers the
+// table's rows would crowd (measured slower with it).
+template <int R>
+__device__ __forceinline__ void near_pairs64_series(const double (&tx)[R], const double (&ty)[R],
                                              const double (&tz)[R], double sx, double sy, double sz,
                                              double gx, double gy, double gz, const DeltaC (&dc)[R],
                                              double (&ax)[R], double (&ay)[R], double (&az)[R])

@@ -206,7 +206,8 @@ __device__ __forceinline__ void far_cluster(const Src &S, int64_t j0, const floa
 template <int R, bool VARD, bool MIXED, bool ZONE, bool STAGE>
 __device__ __forceinline__ void near_cluster(const Src &S, int64_t j0, const float4 *stg,
                                              const DeltaC &dcu, const DeltaC32 &dcu32,
-                                             const float4 *tab, double *zs, Acc<R, VARD, MIXED> &A)
+                                             const float4 *tab, const double2 *tab64, double *zs,
+                                             Acc<R, VARD, MIXED> &A)
 {
     if constexpr (MIXED) {
         float px[R], py[R], pz[R];
@@ -256,11 +257,16 @@ __device__ __forceinline__ void near_cluster(const Src &S, int64_t j0, const flo
         DeltaC dcr[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) dcr[r] = VARD ? A.dc[VARD ? r : 0] : dcu;
-#pragma unroll 2
+        // unrolled twice, except at two targets a lane with the table (two table rows a source
+        // already fill the register file there: 128 registers, four waves per SIMD)
+#pragma unroll (R == 1 || VARD) ? 2 : 1
         for (int j = 0; j < kCluster; ++j) {
             const double *q = S.d + (j0 + j) * 8;
             const double sx = q[0], sy = q[1], sz = q[2], gx = q[3], gy = q[4], gz = q[5];
-            near_pairs64<R>(A.tx, A.ty, A.tz, sx, sy, sz, gx, gy, gz, dcr, A.ax, A.ay, A.az);
+            if constexpr (VARD)
+                near_pairs64_series<R>(A.tx, A.ty, A.tz, sx, sy, sz, gx, gy, gz, dcr, A.ax, A.ay, A.az);
+            else
+                near_pairs64<R>(A.tx, A.ty, A.tz, sx, sy, sz, gx, gy, gz, dcr, tab64, A.ax, A.ay, A.az);
         }
     }
 }
@@ -320,8 +326,8 @@ template <int R, bool VARD, bool MIXED, bool ZONE, bool STAGE, bool BOX>
 __device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec &rec,
                                           const TBlockRec &own, bool grouped, const Src &S,
                                           const double4 *__restrict__ sphere, const float4 *tab,
-                                          double *zs, float4 *stg, double *__restrict__ part, int tb,
-                                          int k, int box, uint2 nc)
+                                          const double2 *tab64, double *zs, float4 *stg,
+                                          double *__restrict__ part, int tb, int k, int box, uint2 nc)
 {
     const uint32_t K = (uint32_t)a.n_ways;
     const int lane = threadIdx.x % kWave;
@@ -390,7 +396,7 @@ __device__ __forceinline__ void pair_item(const PairArgs &a, const TBlockRec &re
             if (((mf >> b) & 1) || (grouped && cluster_is_far(own, sphere[c0 + b])))
                 far_cluster<R, VARD, MIXED, STAGE>(S, j0, stg, A);
             else
-                near_cluster<R, VARD, MIXED, ZONE, STAGE>(S, j0, stg, dcu, dcu32, tab, zs, A);
+                near_cluster<R, VARD, MIXED, ZONE, STAGE>(S, j0, stg, dcu, dcu32, tab, tab64, zs, A);
         }
     }
 
@@ -439,6 +445,10 @@ __global__ __launch_bounds__(G * kWave) void k_pair(PairArgs a, const TBlockRec 
     // Single-precision smoothing table; the first barrier of the work loop publishes it.
     __shared__ float4 sh_tab[MIXED ? kTab32Rows : 1];
     if constexpr (MIXED) load_tab32(sh_tab);
+    // FP64 path with one delta: the double-precision smoothing table, published by the same
+    // barrier.
+    __shared__ double2 sh_tab64[MIXED || VARD ? 1 : kTab64Size2];
+    if constexpr (!MIXED && !VARD) load_tab64(sh_tab64);
     // Mixed path: the double-precision zone's per-target state, R * 6 * 64 doubles per wave.
     __shared__ double sh_zone[MIXED && ZONE ? G * R * 6 * kWave : 1];
     // Mixed path without the zone: each wave's copy of the cluster it works on, so that the
@@ -463,7 +473,7 @@ __global__ __launch_bounds__(G * kWave) void k_pair(PairArgs a, const TBlockRec 
         const int box = BOX ? a.fmm_box_tgt[(int64_t)g * G * R] : 0;
         if (tb < a.n_tblocks)
             pair_item<R, VARD, MIXED, ZONE, STAGE, BOX>(
-                a, recs[g], recs[G > 1 ? n_groups + tb : g], G > 1, S, sphere, sh_tab,
+                a, recs[g], recs[G > 1 ? n_groups + tb : g], G > 1, S, sphere, sh_tab, sh_tab64,
                 sh_zone + (MIXED && ZONE ? w * R * 6 * kWave : 0),
                 sh_stage + (STAGE ? w * 2 * kCluster : 0), part, tb, k, box,
                 MIXED ? counts[g] : make_uint2(0u, 0u));

@@ -127,3 +127,60 @@ def test_double_precision_smoothing_polynomials():
         r1, r2 = f1_f2(q)
         worst_large = max(worst_large, abs(s1 / p - r1) / r1, abs(s2 / p ** 3 - r2) / r2)
     assert worst_large < 2e-15, worst_large
+
+
+def s1_s2(q):
+    """s1 and s2 at q = p^2, 40 digits."""
+    mp.mp.dps = 40
+    q = mp.mpf(q)
+    p = mp.sqrt(q)
+    e = mp.exp(-q) / mp.sqrt(mp.pi)
+    return (float(mp.erf(p) - mp.mpf(2) / 3 * p * (2 * q - 5) * e),
+            float(mp.erf(p) - mp.mpf(2) / 3 * p * (4 * q * q - 14 * q + 3) * e))
+
+
+def test_double_precision_smoothing_table():
+    """The FP64 kernels' table: row 0 gives F1, F2 on 0 <= q < 1 to 4e-16 relative, the octave
+    rows give s1, s2 on 1 <= q < 6.9^2 to 4e-16 absolute (s is of order one there), with the row
+    chosen the way the kernels do (exponent and top two mantissa bits of q) and Horner in double
+    precision (two roundings a step here; the kernels fuse them).  Both ends of every row and
+    random points are checked, and q past the table selects the last row."""
+    src = header()
+    deg = int_const(src, "kTab64Deg")
+    n = int_const(src, "kTab64N")
+    body = src[src.index("kTab64[kTab64N][kTab64Row] = {"):]
+    rows = re.findall(r"\{([^{}]+)\}", body)[:n]
+    tab = np.array([[float(v) for v in r.split(",")] for r in rows])
+    assert tab.shape == (n, 2 * (deg + 2))
+
+    def row_of(q):
+        if not q >= 1.0:
+            return 0
+        m, e = math.frexp(q)                # q = m 2^e, 0.5 <= m < 1
+        i = 1 + 4 * (e - 1) + int((m - 0.5) * 8.0)
+        return i if 1 <= i < n else n - 1
+
+    def evaluate(q):
+        r = tab[row_of(q)]
+        x = (q - r[0]) * r[1]
+        p1, p2 = r[2], r[3]
+        for k in range(1, deg + 1):
+            p1 = p1 * x + r[2 + 2 * k]
+            p2 = p2 * x + r[3 + 2 * k]
+        return p1, p2
+
+    qmax = 6.9 ** 2
+    edges = [0.0, 1.0] + [2.0 ** e * (1 + j / 4) for e in range(6) for j in range(4)]
+    qs = [q for q in edges if q < qmax] + [math.nextafter(q, 0.0) for q in edges[1:] if q < qmax]
+    qs += list(np.random.default_rng(5).uniform(0.0, qmax, 300)) + [1e-9, 0.5, qmax * (1 - 1e-12)]
+    worst = 0.0
+    for q in qs:
+        p1, p2 = evaluate(q)
+        if q < 1.0:
+            e1, e2 = f1_f2(q)
+            worst = max(worst, abs(p1 - e1) / e1, abs(p2 - e2) / e2)
+        else:
+            e1, e2 = s1_s2(q)
+            worst = max(worst, abs(p1 - e1), abs(p2 - e2))
+    assert worst < 4e-16, worst
+    assert row_of(qmax) == n - 1 and row_of(1e300) == n - 1

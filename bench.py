@@ -28,6 +28,7 @@ FLOPS_FAR = 28                                   # plain Stokeslet pair
 FLOPS_NEAR = 49                                  # regularized pair (erf, exp, rsqrt = 1 each)
 RHO_EXACT64 = 6.9                                # s = 1 to double precision beyond this r/delta
 PMC_FILE = os.path.join(ROOT, "profiles", "pmc_pair_kernel.json")
+COPY_BYTES_PMC = 1 << 30                         # the calibration copy of the PMC passes
 PAIR_SOURCES = ["paper_2310_13908_amd/csrc/sl_pair.hip", "paper_2310_13908_amd/csrc/sl_device.h",
                 "paper_2310_13908_amd/csrc/sl_internal.h",
                 "paper_2310_13908_amd/csrc/sl_smoothing_coeffs.h"]
@@ -629,6 +630,53 @@ def secondary_c2(P, ctx, dev, steps, warmup, with_oracle):
     return out, prob, tens
 
 
+def write_pmc(prefix: str) -> None:
+    """profiles/pmc_pair_kernel.json from the FETCH_SIZE and WRITE_SIZE passes of both workloads
+    (rocprofv3 --pmc <counter> --output-format csv -d <prefix>_<c3|c2>_<counter> -o run -- python3
+    bench.py --workload <c3|c2> ... --copy-bytes 1073741824): per-dispatch means of each kernel,
+    scaled to bytes by what the same counter read for the device copy of known size.  Host only."""
+    import csv
+    import re
+
+    def load(path):
+        d = {}
+        for r in csv.DictReader(open(path)):
+            key = re.sub(r"\(.*", "", r["Kernel_Name"].replace("void ", "")
+                         .replace("sl::(anonymous namespace)::", ""))
+            d.setdefault(key, []).append(float(r["Counter_Value"]))
+        return d
+
+    rec = {"pair_kernel_sha": pair_kernel_sha(), "copy_bytes": COPY_BYTES_PMC, "workloads": {}}
+    for tag, wl in (("c3", "rbc_6x256x256_sh8"), ("c2", "rbc_6x64x64_sh8")):
+        F = load(f"{prefix}_{tag}_FETCH_SIZE/run_counter_collection.csv")
+        W = load(f"{prefix}_{tag}_WRITE_SIZE/run_counter_collection.csv")
+        # the calibration copy is the largest copy dispatch (the runtime's small copies are KiB)
+        copy = [k for k in F if "copyBuffer" in k]
+        if len(copy) != 1:
+            raise SystemExit(f"{prefix}_{tag}: no calibration copy")
+        cf, cw = max(F[copy[0]]), max(W[copy[0]])
+        fs, ws = COPY_BYTES_PMC / (cf * 1024), COPY_BYTES_PMC / (cw * 1024)
+        out = {"copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_scale": round(fs, 4),
+               "write_scale": round(ws, 4)}
+        for k in sorted(F):
+            if not (k.startswith("k_pair<") or k == "k_reduce"):
+                continue
+            f, w = sum(F[k]) / len(F[k]), sum(W[k]) / len(W[k])
+            fb, wb = round(f * 1024 * fs), round(w * 1024 * ws)
+            if k == "k_reduce":
+                out[k] = {"fetch_bytes": fb, "write_bytes": wb}
+                continue
+            prec = "mixed" if k.split("<")[1].split(",")[2].strip() == "true" else "fp64"
+            out[prec] = {"kernel": k, "dispatches": len(F[k]), "fetch_kib": round(f, 1),
+                         "write_kib": round(w, 1), "fetch_bytes": fb, "write_bytes": wb,
+                         "hbm_bytes_per_launch": fb + wb}
+        rec["workloads"][wl] = out
+    with open(PMC_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(rec, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -650,7 +698,13 @@ def main():
                          "(for counter runs of the smaller case)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one device copy of this many bytes (PMC calibration)")
+    ap.add_argument("--write-pmc", metavar="PREFIX",
+                    help="write the stored HBM traffic from the csv output of the FETCH_SIZE and "
+                         "WRITE_SIZE passes under PREFIX_<c3|c2>_<counter>/ and exit (no GPU)")
     args = ap.parse_args()
+    if args.write_pmc:
+        write_pmc(args.write_pmc)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the sum would shard "
               "over targets after one all-gather of the sources); run with --gpus 1.",

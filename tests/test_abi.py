@@ -67,3 +67,48 @@ def test_pair_kernel_hash_ignores_comments_only():
     for p in bench.PAIR_SOURCES:
         assert os.path.exists(os.path.join(bench.ROOT, p)), p
     assert re.fullmatch(r"[0-9a-f]{16}", bench.pair_kernel_sha())
+
+
+def test_write_pmc_scales_by_the_calibration_copy(tmp_path, monkeypatch):
+    """bench.py --write-pmc: per-dispatch means of each kernel, scaled to bytes by what the same
+    counter read for the 1 GiB copy (the largest copy dispatch; the runtime's small copies are
+    ignored), keyed by the pair kernel's hash."""
+    import csv
+    import json
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    hdr = ["Kernel_Name", "Counter_Name", "Counter_Value"]
+    fetch = {"__amd_rocclr_copyBuffer": [2.0, 524288.0, 1.5],
+             "void sl::(anonymous namespace)::k_pair<1, false, true, false, 4, false>(sl::PairArgs)": [100.0, 300.0],
+             "void sl::(anonymous namespace)::k_pair<2, false, false, false, 1, false>(sl::PairArgs)": [1000.0],
+             "void sl::(anonymous namespace)::k_reduce(double const*, int)": [64.0],
+             "void at::native::elementwise_kernel(int)": [9e9]}
+    write = {"__amd_rocclr_copyBuffer": [1.0, 1048576.0],
+             "void sl::(anonymous namespace)::k_pair<1, false, true, false, 4, false>(sl::PairArgs)": [40.0, 40.0],
+             "void sl::(anonymous namespace)::k_pair<2, false, false, false, 1, false>(sl::PairArgs)": [80.0],
+             "void sl::(anonymous namespace)::k_reduce(double const*, int)": [8.0]}
+    for tag in ("c3", "c2"):
+        for counter, rows in (("FETCH_SIZE", fetch), ("WRITE_SIZE", write)):
+            d = tmp_path / f"p_{tag}_{counter}"
+            d.mkdir()
+            with open(d / "run_counter_collection.csv", "w", newline="") as fh:
+                w = csv.writer(fh)
+                w.writerow(hdr)
+                for k, vals in rows.items():
+                    for v in vals:
+                        w.writerow([k, counter, v])
+    out = tmp_path / "pmc.json"
+    monkeypatch.setattr(bench, "PMC_FILE", str(out))
+    bench.write_pmc(str(tmp_path / "p"))
+    rec = json.load(open(out))
+    assert rec["pair_kernel_sha"] == bench.pair_kernel_sha()
+    wl = rec["workloads"]["rbc_6x256x256_sh8"]
+    assert wl["fetch_scale"] == 2.0 and wl["write_scale"] == 1.0
+    assert wl["mixed"]["kernel"] == "k_pair<1, false, true, false, 4, false>"
+    assert wl["mixed"]["dispatches"] == 2
+    assert wl["mixed"]["fetch_bytes"] == 200 * 1024 * 2 and wl["mixed"]["write_bytes"] == 40 * 1024
+    assert wl["mixed"]["hbm_bytes_per_launch"] == 200 * 2048 + 40 * 1024
+    assert wl["fp64"]["hbm_bytes_per_launch"] == 1000 * 2048 + 80 * 1024
+    assert wl["k_reduce"] == {"fetch_bytes": 64 * 2048, "write_bytes": 8 * 1024}
+    assert set(rec["workloads"]) == {"rbc_6x256x256_sh8", "rbc_6x64x64_sh8"}

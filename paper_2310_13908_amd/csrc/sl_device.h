@@ -164,27 +164,29 @@ __device__ __forceinline__ void near_pair64(double tx, double ty, double tz,
 
 // The double-precision smoothing table (kTab64) in LDS, copied by the threads of a workgroup (the
 // caller synchronizes afterwards): per row, {centre, 1/half width}, then the pairs (c1, c2) from
-// the highest power down, as double2.
+// the highest power down, as double2.  Row kTab64N, past the table, is the identity: local
+// variable 0 and constant term 1, so that it gives s1 = s2 = 1 exactly.
 constexpr int kTab64Row2 = kTab64Row / 2;
-constexpr int kTab64Size2 = kTab64N * kTab64Row2;
+constexpr int kTab64Size2 = (kTab64N + 1) * kTab64Row2;
 
 __device__ __forceinline__ void load_tab64(double2 *tab)
 {
-    for (int i = threadIdx.x; i < kTab64Size2; i += blockDim.x)
-        tab[i] = make_double2(kTab64[i / kTab64Row2][2 * (i % kTab64Row2)],
-                              kTab64[i / kTab64Row2][2 * (i % kTab64Row2) + 1]);
+    for (int i = threadIdx.x; i < kTab64Size2; i += blockDim.x) {
+        const int row = i / kTab64Row2, k = i % kTab64Row2;
+        tab[i] = row < kTab64N ? make_double2(kTab64[row][2 * k], kTab64[row][2 * k + 1])
+                               : (k == kTab64Row2 - 1 ? make_double2(1.0, 1.0)
+                                                      : make_double2(0.0, 0.0));
+    }
 }
 
-// Table row of q = (r/delta)^2: 0 for q < 1, else 1 + 4 e + j for q in 2^e [1 + j/4, 1 + (j+1)/4)
-// (exponent and top two mantissa bits); anything past the table, infinity included, takes the
-// last row, and the caller selects those lanes out.
+// Table row of q = (r/delta)^2 >= 0 from the high word of its bits, whose bits 18 and up hold
+// the biased exponent and the top two mantissa bits: 0 for q < 1, 1 + 4 e + j for q in
+// 2^e [1 + j/4, 1 + (j+1)/4), and the identity row kTab64N past the table (q >= 48, infinity
+// and NaN included).
 __device__ __forceinline__ int tab64_row(double q)
 {
-    if (!(q >= 1.0)) return 0;
-    const int e = __builtin_amdgcn_frexp_exp(q) - 1;
-    const int j = (int)((__builtin_amdgcn_frexp_mant(q) - 0.5) * 8.0);
-    const int i = 1 + 4 * e + j;
-    return (i >= 1 && i < kTab64N) ? i : kTab64N - 1;
+    const int i = (__double2hiint(q) >> 18) - (4 * 1023 - 1);
+    return min(max(i, 0), kTab64N);
 }
 
 // Row 0: F1(q) = s1/p and F2(q) = s2/p^3; other rows: s1 and s2; a polynomial of degree
@@ -206,8 +208,10 @@ __device__ __forceinline__ void smoothing64(double q, const double2 *tab, int ro
 }
 
 // One source against the R targets of a lane, in double precision, the smoothing from the table
-// in LDS (`tab`, load_tab64) for every lane within 6.9 delta, evaluated wherever one lane of the
-// wavefront needs it: one branch, one table row a pair.
+// in LDS (`tab`, load_tab64), evaluated wherever one lane of the wavefront is within 6.9 delta:
+// one branch, one table row a pair.  Lanes past the table take its identity row, which leaves
+// the plain kernel unchanged, and lanes between 6.9 delta and the table's end (s = 1 to double
+// precision there) take s from the table.
 template <int R>
 __device__ __forceinline__ void near_pairs64(const double (&tx)[R], const double (&ty)[R],
                                              const double (&tz)[R], double sx, double sy, double sz,
@@ -215,8 +219,7 @@ __device__ __forceinline__ void near_pairs64(const double (&tx)[R], const double
                                              const double2 *tab, double (&ax)[R], double (&ay)[R],
                                              double (&az)[R])
 {
-    double dx[R], dy[R], dz[R], r2[R], ri[R], q[R], K1[R], K2[R];
-    bool sm[R];
+    double dx[R], dy[R], dz[R], r2[R], q[R], K1[R], K2[R];
     bool any = false;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -224,12 +227,10 @@ __device__ __forceinline__ void near_pairs64(const double (&tx)[R], const double
         dy[r] = ty[r] - sy;
         dz[r] = tz[r] - sz;
         r2[r] = fma(dx[r], dx[r], fma(dy[r], dy[r], dz[r] * dz[r]));
-        ri[r] = rsqrt64(r2[r] > 0.0 ? r2[r] : 1.0);
-        K1[r] = ri[r];
-        K2[r] = ri[r] * ri[r] * ri[r];
+        K1[r] = rsqrt64(r2[r] > 0.0 ? r2[r] : 1.0);
+        K2[r] = K1[r] * K1[r] * K1[r];
         q[r] = r2[r] * dc[r].id2;
-        sm[r] = r2[r] < dc[r].cut2;
-        any = any || sm[r];
+        any = any || r2[r] < dc[r].cut2;
     }
     if (__builtin_amdgcn_ballot_w64(any)) {
 #pragma unroll
@@ -237,10 +238,10 @@ __device__ __forceinline__ void near_pairs64(const double (&tx)[R], const double
             const int row = tab64_row(q[r]);
             double p1, p2;
             smoothing64(q[r], tab, row, p1, p2);
-            const double k1 = row == 0 ? p1 * dc[r].id : ri[r] * p1;
-            const double k2 = row == 0 ? p2 * dc[r].id3 : (ri[r] * ri[r] * ri[r]) * p2;
-            K1[r] = sm[r] ? k1 : K1[r];
-            K2[r] = sm[r] ? k2 : K2[r];
+            // row 0 holds F1 = s1/p and F2 = s2/p^3 (finite at r = 0), the others s1 and s2
+            const bool inner = row == 0;
+            K1[r] = (inner ? dc[r].id : K1[r]) * p1;
+            K2[r] = (inner ? dc[r].id3 : K2[r]) * p2;
         }
     }
 #pragma unroll

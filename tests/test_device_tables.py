@@ -1,6 +1,7 @@
 """CPU checks of the constant tables that the HIP kernels evaluate, against 40-digit values of
 the smoothing factors of Sec. 3.4 (mpmath, independent of both the kernels and the oracle)."""
 import math
+import struct
 import os
 import re
 
@@ -141,10 +142,12 @@ def s1_s2(q):
 
 def test_double_precision_smoothing_table():
     """The FP64 kernels' table: row 0 gives F1, F2 on 0 <= q < 1 to 4e-16 relative, the octave
-    rows give s1, s2 on 1 <= q < 6.9^2 to 4e-16 absolute (s is of order one there), with the row
-    chosen the way the kernels do (exponent and top two mantissa bits of q) and Horner in double
+    rows give s1, s2 on 1 <= q < 48 (past 6.9^2 = 47.61, where s = 1 to double precision) to
+    4e-16 absolute (s is of order one there), with the row chosen the way the kernels do (bits 18
+    and up of the high word of q: biased exponent and top two mantissa bits) and Horner in double
     precision (two roundings a step here; the kernels fuse them).  Both ends of every row and
-    random points are checked, and q past the table selects the last row."""
+    random points are checked; the row choice agrees with frexp's exponent and mantissa; q past
+    the table takes the identity row the kernels append, which gives s1 = s2 = 1 exactly."""
     src = header()
     deg = int_const(src, "kTab64Deg")
     n = int_const(src, "kTab64N")
@@ -152,13 +155,20 @@ def test_double_precision_smoothing_table():
     rows = re.findall(r"\{([^{}]+)\}", body)[:n]
     tab = np.array([[float(v) for v in r.split(",")] for r in rows])
     assert tab.shape == (n, 2 * (deg + 2))
+    identity = np.zeros(2 * (deg + 2))
+    identity[-2:] = 1.0
+    tab = np.vstack([tab, identity])
 
     def row_of(q):
-        if not q >= 1.0:
+        hi = struct.unpack("<Q", struct.pack("<d", q))[0] >> 32
+        hi = hi - (1 << 32) if hi >= 1 << 31 else hi       # the kernels' int
+        return min(max((hi >> 18) - (4 * 1023 - 1), 0), n)
+
+    def row_by_frexp(q):
+        if q < 1.0:
             return 0
         m, e = math.frexp(q)                # q = m 2^e, 0.5 <= m < 1
-        i = 1 + 4 * (e - 1) + int((m - 0.5) * 8.0)
-        return i if 1 <= i < n else n - 1
+        return min(1 + 4 * (e - 1) + int((m - 0.5) * 8.0), n)
 
     def evaluate(q):
         r = tab[row_of(q)]
@@ -169,12 +179,13 @@ def test_double_precision_smoothing_table():
             p2 = p2 * x + r[3 + 2 * k]
         return p1, p2
 
-    qmax = 6.9 ** 2
+    qend = 48.0
     edges = [0.0, 1.0] + [2.0 ** e * (1 + j / 4) for e in range(6) for j in range(4)]
-    qs = [q for q in edges if q < qmax] + [math.nextafter(q, 0.0) for q in edges[1:] if q < qmax]
-    qs += list(np.random.default_rng(5).uniform(0.0, qmax, 300)) + [1e-9, 0.5, qmax * (1 - 1e-12)]
+    qs = [q for q in edges if q < qend] + [math.nextafter(q, 0.0) for q in edges[1:] if q <= qend]
+    qs += list(np.random.default_rng(5).uniform(0.0, qend, 300)) + [1e-9, 0.5, 6.9 ** 2]
     worst = 0.0
     for q in qs:
+        assert row_of(q) == row_by_frexp(q), q
         p1, p2 = evaluate(q)
         if q < 1.0:
             e1, e2 = f1_f2(q)
@@ -183,4 +194,8 @@ def test_double_precision_smoothing_table():
             e1, e2 = s1_s2(q)
             worst = max(worst, abs(p1 - e1), abs(p2 - e2))
     assert worst < 4e-16, worst
-    assert row_of(qmax) == n - 1 and row_of(1e300) == n - 1
+    assert row_of(math.nextafter(qend, 0.0)) == n - 1 and row_of(-0.0) == 0
+    for q in (qend, 60.0, 1e300, math.inf, math.nan):
+        assert row_of(q) == n
+    for q in (qend, 60.0, 1e300):
+        assert evaluate(q) == (1.0, 1.0)

@@ -254,107 +254,6 @@ __device__ __forceinline__ void near_pairs64(const double (&tx)[R], const double
     }
 }
 
-// The same with the series for q < 1 and the exp/erfc form beyond, each evaluated wherever one
-// lane of the wavefront needs it (no table): the per-target-delta kernels, whose registers the
-// table's rows would crowd (measured slower with it).
-template <int R>
-__device__ __forceinline__ void near_pairs64_series(const double (&tx)[R], const double (&ty)[R],
-                                             const double (&tz)[R], double sx, double sy, double sz,
-                                             double gx, double gy, double gz, const DeltaC (&dc)[R],
-                                             double (&ax)[R], double (&ay)[R], double (&az)[R])
-{
-    double dx[R], dy[R], dz[R], r2[R], ri[R], q[R], K1[R], K2[R];
-    bool sm[R], lg[R];
-    bool any_sm = false, any_lg = false;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        dx[r] = tx[r] - sx;
-        dy[r] = ty[r] - sy;
-        dz[r] = tz[r] - sz;
-        r2[r] = fma(dx[r], dx[r], fma(dy[r], dy[r], dz[r] * dz[r]));
-        ri[r] = rsqrt64(r2[r] > 0.0 ? r2[r] : 1.0);
-        K1[r] = ri[r];
-        K2[r] = ri[r] * ri[r] * ri[r];
-        q[r] = r2[r] * dc[r].id2;
-        sm[r] = q[r] < kSeriesQMax;
-        lg[r] = !sm[r] && r2[r] < dc[r].cut2;
-        any_sm = any_sm || sm[r];
-        any_lg = any_lg || lg[r];
-    }
-    if (__builtin_amdgcn_ballot_w64(any_sm)) {
-        double x[R], f1[R], f2[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            x[r] = fmin(q[r], kSeriesQMax) - kSeriesMid;
-            f1[r] = kF1[kSeriesDeg];
-            f2[r] = kF2[kSeriesDeg];
-        }
-#pragma unroll
-        for (int k = kSeriesDeg - 1; k >= 0; --k) {
-            const double c1 = sconst(kF1[k]), c2 = sconst(kF2[k]);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                f1[r] = fma(f1[r], x[r], c1);
-                f2[r] = fma(f2[r], x[r], c2);
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            K1[r] = sm[r] ? f1[r] * dc[r].id : K1[r];
-            K2[r] = sm[r] ? f2[r] * dc[r].id3 : K2[r];
-        }
-    }
-    if (__builtin_amdgcn_ballot_w64(any_lg)) {
-        double p[R], n[R], f[R], e[R], y[R], t[R], g[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const double qq = fmin(fmax(q[r], kSeriesQMax), kRhoExact64 * kRhoExact64);
-            p[r] = (r2[r] * ri[r]) * dc[r].id;
-            n[r] = rint(qq * kLog2E);
-            f[r] = fma(-n[r], kLn2Lo, fma(-n[r], kLn2Hi, qq));
-            e[r] = kExpC[kExpDeg];
-            const double den = kGK + p[r];
-            double yy = __builtin_amdgcn_rcp(den);
-            double ee = fma(-den, yy, 1.0);
-            yy = fma(yy, ee, yy);
-            ee = fma(-den, yy, 1.0);
-            y[r] = fma(yy, ee, yy);
-            t[r] = fma(kGK, y[r], -kGMid);
-            g[r] = kG[kGDeg];
-        }
-#pragma unroll
-        for (int k = kExpDeg - 1; k >= 0; --k) {
-            const double c = sconst(kExpC[k]);
-#pragma unroll
-            for (int r = 0; r < R; ++r) e[r] = fma(e[r], -f[r], c);
-        }
-#pragma unroll
-        for (int i = kGDeg - 1; i >= 0; --i) {
-            const double c = sconst(kG[i]);
-#pragma unroll
-            for (int r = 0; r < R; ++r) g[r] = fma(g[r], t[r], c);
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const double E = ldexp(e[r], -(int)n[r]);
-            const double qq = fmin(fmax(q[r], kSeriesQMax), kRhoExact64 * kRhoExact64);
-            const double c0p = kC0 * p[r];
-            const double A1 = fma(c0p, fma(2.0, qq, -5.0), g[r]);
-            const double A2 = fma(c0p, fma(qq, fma(4.0, qq, -14.0), 3.0), g[r]);
-            K1[r] = lg[r] ? ri[r] * fma(-E, A1, 1.0) : K1[r];
-            K2[r] = lg[r] ? (ri[r] * ri[r] * ri[r]) * fma(-E, A2, 1.0) : K2[r];
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const double gd = fma(gx, dx[r], fma(gy, dy[r], gz * dz[r]));
-        const double c = gd * K2[r];
-        ax[r] = fma(K1[r], gx, fma(c, dx[r], ax[r]));
-        ay[r] = fma(K1[r], gy, fma(c, dy[r], ay[r]));
-        az[r] = fma(K1[r], gz, fma(c, dz[r], az[r]));
-    }
-}
-
 // Pair of the mixed path's double-precision zone (p < rho64, including r = 0): as near_pair64,
 // without 1/r where q < 1 (always so for rho64 <= 1).
 __device__ __forceinline__ void zone_pair64(double tx, double ty, double tz,

@@ -257,16 +257,13 @@ __device__ __forceinline__ void near_cluster(const Src &S, int64_t j0, const flo
         DeltaC dcr[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) dcr[r] = VARD ? A.dc[VARD ? r : 0] : dcu;
-        // unrolled twice, except at two targets a lane with the table (two table rows a source
-        // already fill the register file there: 128 registers, four waves per SIMD)
+        // unrolled twice, except at two or more targets a lane with one delta (their table rows
+        // already fill the register file there)
 #pragma unroll (R == 1 || VARD) ? 2 : 1
         for (int j = 0; j < kCluster; ++j) {
             const double *q = S.d + (j0 + j) * 8;
             const double sx = q[0], sy = q[1], sz = q[2], gx = q[3], gy = q[4], gz = q[5];
-            if constexpr (VARD)
-                near_pairs64_series<R>(A.tx, A.ty, A.tz, sx, sy, sz, gx, gy, gz, dcr, A.ax, A.ay, A.az);
-            else
-                near_pairs64<R>(A.tx, A.ty, A.tz, sx, sy, sz, gx, gy, gz, dcr, tab64, A.ax, A.ay, A.az);
+            near_pairs64<R>(A.tx, A.ty, A.tz, sx, sy, sz, gx, gy, gz, dcr, tab64, A.ax, A.ay, A.az);
         }
     }
 }
@@ -445,10 +442,9 @@ __global__ __launch_bounds__(G * kWave) void k_pair(PairArgs a, const TBlockRec 
     // Single-precision smoothing table; the first barrier of the work loop publishes it.
     __shared__ float4 sh_tab[MIXED ? kTab32Rows : 1];
     if constexpr (MIXED) load_tab32(sh_tab);
-    // FP64 path with one delta: the double-precision smoothing table, published by the same
-    // barrier.
-    __shared__ double2 sh_tab64[MIXED || VARD ? 1 : kTab64Size2];
-    if constexpr (!MIXED && !VARD) load_tab64(sh_tab64);
+    // FP64 path: the double-precision smoothing table, published by the same barrier.
+    __shared__ double2 sh_tab64[MIXED ? 1 : kTab64Size2];
+    if constexpr (!MIXED) load_tab64(sh_tab64);
     // Mixed path: the double-precision zone's per-target state, R * 6 * 64 doubles per wave.
     __shared__ double sh_zone[MIXED && ZONE ? G * R * 6 * kWave : 1];
     // Mixed path without the zone: each wave's copy of the cluster it works on, so that the

@@ -24,9 +24,10 @@
 //     then read about 1/K of the source records, which stay in each XCD's L2: at 6 x 256^2
 //     points this cuts the kernel's fetches from memory twelvefold, at the same speed.
 //   FP64 path: way k takes the ranks congruent to k mod K, and the items run group by group.
-//     Contiguous ranges measured slower here (13% at 6 x 256^2 points): a way's near clusters
-//     then come in one run, and the scalar-heavy near-field code of the waves sharing a compute
-//     unit coincides more often; the interleaved deal keeps every wave's mix even.
+//     Contiguous ranges measured slower here (7% at 6 x 256^2 points with the items way by way,
+//     10% group by group, 16% at 6 x 64^2): a way's near clusters then come in one spatial run,
+//     so the closest ones, where most pairs need the smoothing, fall to few ways; the interleaved
+//     deal keeps every way's mix even.
 //   k_tblock: per target group, bounding sphere and far threshold;
 //   k_counts: per target group, the numbers of far and near clusters (mixed path);
 //   k_pair:   occupancy-sized grid; every workgroup pulls work items off a counter;

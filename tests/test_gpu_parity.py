@@ -190,17 +190,24 @@ def test_per_target_delta_above_2_17_targets(ctx, precision, rho64):
         ctx.set_rho64(0.0)
 
 
-@pytest.mark.parametrize("precision,rho64", [("fp64", 0.0), ("mixed", 0.0), ("mixed", 1.0)])
-def test_smoothing_profile_single_source(ctx, precision, rho64):
-    """One source, targets at r/delta from 0 (coincident) through the series/fit switch (0.5)
-    and the exact-smoothing cut (6.9) to 9, in many directions: every target's velocity is a
-    single pair term, so this checks the device s1/r and s2/r^3 per target, not in a norm.
-    Mixed runs once without a double-precision zone (the default) and once with rho64 = 1."""
+@pytest.mark.parametrize("precision,rho64,per_target", [("fp64", 0.0, False), ("fp64", 0.0, True),
+                                                        ("mixed", 0.0, False), ("mixed", 1.0, False)])
+def test_smoothing_profile_single_source(ctx, precision, rho64, per_target):
+    """One source, targets at r/delta from 0 (coincident) through the exact-smoothing cut (6.9)
+    to 9, in many directions: every target's velocity is a single pair term, so this checks the
+    device s1/r and s2/r^3 per target, not in a norm.  The points include both sides of every
+    boundary of the double-precision table's rows (q = (r/delta)^2 = 1 and 2^e (1 + j/4)) and of
+    its end at q = 48, past which its identity row applies.  FP64 runs with one delta and with the
+    same delta given per target (the per-target-delta kernel); mixed without a double-precision
+    zone (the default) and with rho64 = 1."""
     import oracle
     rng = np.random.default_rng(17)
     delta = 0.037
+    edges = np.array([1.0] + [2.0 ** e * (1 + j / 4) for e in range(6) for j in range(4)] + [48.0])
+    rho_edges = np.sqrt(np.concatenate([edges * (1 - 1e-13), edges, edges * (1 + 1e-13)]))
     rho = np.concatenate([[0.0, 1e-12, 1e-8, 1e-5, 1e-3, 0.1, 0.4999, 0.5, 0.5001],
-                          np.linspace(0.0, 9.0, 1801)[1:], [4.9999, 5.0, 5.0001, 6.8999, 6.9, 6.9001]])
+                          np.linspace(0.0, 9.0, 1801)[1:], [4.9999, 5.0, 5.0001, 6.8999, 6.9, 6.9001],
+                          rho_edges])
     dirs = rng.standard_normal((rho.size, 3))
     dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
     src = np.array([[0.31, -0.72, 0.18]])
@@ -208,7 +215,11 @@ def test_smoothing_profile_single_source(ctx, precision, rho64):
     g = np.array([[0.8, -1.3, 0.45]])
     ctx.set_rho64(rho64)
     try:
-        u = gpu_eval(ctx, src, [0.02], g, delta, targets=T, precision=precision)
+        if per_target:
+            u = gpu_eval(ctx, src, [0.02], g, 0.0, targets=T, delta_tgt=np.full(rho.size, delta),
+                         precision=precision)
+        else:
+            u = gpu_eval(ctx, src, [0.02], g, delta, targets=T, precision=precision)
     finally:
         ctx.set_rho64(0.0)
     ref = oracle.single_layer(src, [0.02], g, delta, targets=T)

@@ -730,7 +730,7 @@ sl_status sl_eval_fmm(sl_ctx *ctx, sl_precision prec, int64_t n, const double *x
     const size_t b_off = take((size_t)(k + 1) * 8), b_cnts = take((size_t)k * 8), b_boxc = take((size_t)4 * k * 8);
     const size_t b_bdl = take((size_t)k * 8), b_near = take((size_t)k * k), b_bsurf = take((size_t)np / kWave * 4);
     const size_t b_cx = take(npc * 8), b_cy = take(npc * 8), b_cz = take(npc * 8), b_cperm = take(npc * 4);
-    const size_t b_btc = take((size_t)npc / kWave * 4), b_chk = take((size_t)3 * npc * 8);
+    const size_t b_btc = take((size_t)npc / kWave * 4);
     const size_t b_vx = take((size_t)k * ne * 8), b_vy = take((size_t)k * ne * 8), b_vz = take((size_t)k * ne * 8);
     const size_t b_eqp = take((size_t)3 * npe * 8), b_erec = take(npe * 64), b_e32 = mixed ? take(npe * 32) : 0;
     const size_t b_esph = take(npe / kCluster * sizeof(double4)), b_bse = take((size_t)npe / kCluster * 4);
